@@ -1,0 +1,437 @@
+"""Pins of the CPU oracle against facts the paper and mathematics fix.
+
+Each test checks an oracle function against something other than itself:
+closed forms, invariants from the stability section (Sec. 3.3), the
+convergence table of Sec. 3.4, special cases with known answers, a dense LU
+solve, brute force on tiny inputs.  They are chosen so that a dropped term, a
+wrong sign, a wrong index or a transposed operand fails at least one of them.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rand_padded(rng, n, lo=0.0, hi=1.0):
+    import oracle
+
+    return rng.uniform(lo, hi, size=oracle.padded_shape(n))
+
+
+# ------------------------------------------------------------- face gradient
+
+
+@pytest.mark.parametrize("d", [0, 1, 2, 3])
+def test_face_gradient_exact_for_quadratics(orc, d):
+    """The reduced diamond cell gradient on a face equals the exact gradient of
+    any quadratic polynomial at the face centre (normal: centred difference of
+    a quadratic; tangential: mean of two centred differences of a linear
+    function)."""
+    rng = np.random.default_rng(5 + d)
+    n = (5, 4, 4, 3)
+    h = 0.7
+    Q = rng.normal(size=(4, 4))
+    Q = Q + Q.T
+    bvec = rng.normal(size=4)
+    idx = np.meshgrid(*[np.arange(s) for s in orc.padded_shape(n)], indexing="ij")  # t,z,y,x
+    X = np.stack([idx[3], idx[2], idx[1], idx[0]], axis=-1).astype(float) * h   # x,y,z,t coords
+    u = 0.5 * np.einsum("...i,ij,...j->...", X, Q, X) + X @ bvec + 0.3
+    g = orc.face_gradient(n, u, d, h)
+    e = np.zeros(4)
+    e[d] = 0.5 * h
+    exact = (X + e) @ Q + bvec
+    mask = np.zeros(orc.padded_shape(n), dtype=bool)
+    sl = [slice(1, n[3] + 1), slice(1, n[2] + 1), slice(1, n[1] + 1), slice(1, n[0] + 1)]
+    sl[3 - d] = slice(0, n[d] + 1)
+    mask[tuple(sl)] = True
+    assert np.abs(g[mask] - exact[mask]).max() < 1e-12
+
+
+# ---------------------------------------------------------- edge detector G
+
+
+def test_face_g_constant_image_and_K0(orc):
+    n = (6, 5, 4, 3)
+    I = np.full(orc.interior_shape(n), 0.37)
+    G = orc.face_g(n, I, I, 1.0, 1000.0, 0.5, 0.5)
+    assert np.array_equal(G, np.ones_like(G))
+    rng = np.random.default_rng(1)
+    J = rng.normal(size=orc.interior_shape(n))
+    G0 = orc.face_g(n, J, J * 2, 1.0, 0.0, 0.5, 0.5)
+    assert np.array_equal(G0, np.ones_like(G0))
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2, 3])
+def test_face_g_linear_ramp(orc, axis):
+    """I = a * coordinate along `axis`: on faces whose whole stencil is interior
+    G = 1/(1 + K ((delta+vartheta) a)^2) in the ramp direction, and on faces
+    normal to other directions the gradient is also (a along axis) -> same."""
+    n = (7, 6, 6, 5)
+    a, h, K, de, th = 0.03, 1.0, 1000.0, 0.6, 0.3
+    shp = orc.interior_shape(n)
+    coord = np.indices(shp)[3 - axis].astype(float)
+    I0 = a * coord * h
+    G = orc.face_g(n, I0, I0, h, K, de, th)
+    want = 1.0 / (1.0 + K * ((de + th) * a) ** 2)
+    for d in range(4):
+        # faces with P and P+e_d interior and all tangential neighbours interior
+        sl = [slice(2, n[3]), slice(2, n[2]), slice(2, n[1]), slice(2, n[0])]
+        sl[3 - d] = slice(1, n[d])
+        got = G[d][tuple(sl)]
+        assert np.allclose(got, want, rtol=0, atol=1e-14), (d, got.min(), got.max(), want)
+
+
+def test_face_g_weights_sum_of_norms(orc):
+    """g is applied to delta*|grad I0| + vartheta*|grad ITH| (sum of norms, Sec. 3.1):
+    ramps along different axes in I0 and ITH give norms a and b, not |(a,b)|."""
+    n = (7, 6, 6, 5)
+    shp = orc.interior_shape(n)
+    I0 = 0.02 * np.indices(shp)[3].astype(float)     # ramp in x
+    I1 = 0.05 * np.indices(shp)[2].astype(float)     # ramp in y
+    G = orc.face_g(n, I0, I1, 1.0, 1000.0, 0.5, 0.5)
+    want = 1.0 / (1.0 + 1000.0 * (0.5 * 0.02 + 0.5 * 0.05) ** 2)
+    assert abs(G[0][2, 2, 2, 3] - want) < 1e-14
+
+
+# ------------------------------------------------------------------- LHE
+
+
+@pytest.mark.parametrize("axis,mode", [(0, 1), (0, 3), (1, 2), (2, 1), (3, 2)])
+def test_lhe_cosine_eigenmode(orc, axis, mode):
+    """cos(pi m (i-1/2)/N) along one axis is an eigenvector of the cell-centred
+    zero-Neumann Laplacian with eigenvalue (4/h^2) sin^2(pi m/(2N)), so one
+    implicit step divides it by 1 + tau (4/h^2) sin^2(pi m/(2N))."""
+    n = (8, 7, 6, 5)
+    h, tau = 1.3, 0.4
+    shp = orc.interior_shape(n)
+    i = np.indices(shp)[3 - axis].astype(float) + 1.0
+    N = n[axis]
+    v = np.cos(np.pi * mode * (i - 0.5) / N)
+    J, it = orc.lhe_step(n, v, h, tau, 1.5, 1e-14)
+    lam = (4.0 / h ** 2) * np.sin(np.pi * mode / (2 * N)) ** 2
+    assert np.abs(J - v / (1.0 + tau * lam)).max() < 1e-12
+
+
+def test_lhe_mass_constant_dmp(orc):
+    rng = np.random.default_rng(3)
+    n = (6, 5, 5, 4)
+    v = rng.uniform(-1, 2, size=orc.interior_shape(n))
+    J, _ = orc.lhe_step(n, v, 1.0, 0.7, 1.5, 1e-14)
+    assert abs(J.sum() - v.sum()) < 1e-10          # zero flux through the boundary
+    assert J.min() >= v.min() - 1e-12 and J.max() <= v.max() + 1e-12
+    c, _ = orc.lhe_step(n, np.full_like(v, 4.25), 1.0, 0.7)
+    assert np.abs(c - 4.25).max() < 1e-13
+
+
+# ---------------------------------------------------- balls / threshold / rescale
+
+
+def _centres(lst):
+    import oracle
+
+    return np.array(lst, dtype=oracle.CENTRE_DTYPE)
+
+
+def test_owner_map_brute_force(orc):
+    rng = np.random.default_rng(7)
+    n = (12, 11, 9, 3)
+    cs = _centres([(rng.uniform(0, 11), rng.uniform(0, 10), rng.uniform(0, 8), f)
+                   for f in range(3) for _ in range(3)] + [(4.0, 4.0, 4.0, 1), (6.0, 4.0, 4.0, 1)])
+    r = 3.5
+    own = orc.owner_map(n, cs, r)
+    for l in range(n[3]):
+        for k in range(n[2]):
+            for j in range(n[1]):
+                for i in range(n[0]):
+                    best, bd = -1, None
+                    for m, c in enumerate(cs):
+                        if c["frame"] != l:
+                            continue
+                        d2 = (i - float(c["x"])) ** 2 + (j - float(c["y"])) ** 2 + (k - float(c["z"])) ** 2
+                        if d2 <= r * r and (bd is None or d2 < bd):
+                            best, bd = m, d2
+                    assert own[l, k, j, i] == best
+    # the two centres at distance 2 tie on the plane x=5: lowest index wins
+    assert own[1, 4, 4, 5] == 9
+
+
+def test_threshold_binary_image_is_identity(orc):
+    """On a two-valued image every ball's alpha/beta are the two values and the
+    threshold lies between them, so I^TH = I0 (remark in Sec. 4)."""
+    rng = np.random.default_rng(11)
+    n = (10, 10, 8, 3)
+    I0 = np.where(rng.random(orc.interior_shape(n)) < 0.4, 0.9, 0.1)
+    cs = _centres([(4.5, 5.0, 3.5, f) for f in range(3)] + [(2.0, 2.0, 2.0, 2)])
+    own = orc.owner_map(n, cs, 3.0)
+    for lam in (0.1, 0.5, 0.87):
+        ITH = orc.threshold(n, I0, cs, 3.0, lam, own)
+        assert np.array_equal(ITH, I0)
+
+
+def test_threshold_two_levels_inside_ball(orc):
+    rng = np.random.default_rng(12)
+    n = (10, 10, 8, 2)
+    I0 = rng.uniform(0, 1, size=orc.interior_shape(n))
+    cs = _centres([(4.5, 5.0, 3.5, 0), (5.0, 4.0, 3.0, 1)])
+    own = orc.owner_map(n, cs, 3.0)
+    ITH = orc.threshold(n, I0, cs, 3.0, 0.5, own)
+    for m in range(2):
+        vals = ITH[own == m]
+        src = I0[own == m]
+        assert set(np.unique(vals)) == {src.min(), src.max()}
+        th = 0.5 * src.min() + 0.5 * src.max()
+        assert np.array_equal(vals == src.max(), src >= th)
+    assert np.array_equal(ITH[own < 0], I0[own < 0])
+
+
+def test_rescale_maps_balls_to_unit_interval(orc):
+    rng = np.random.default_rng(13)
+    n = (12, 12, 10, 3)
+    u = rand_padded(rng, n, 0.2, 0.7)
+    cs = _centres([(5.0, 5.0, 4.0, f) for f in range(3)])
+    own = orc.owner_map(n, cs, 3.0)
+    ur = orc.rescale(n, u, cs, 3.0, own)
+    ui, ri = orc.interior(u), orc.interior(ur)
+    for m in range(3):
+        assert ri[own == m].min() == 0.0 and ri[own == m].max() == 1.0
+    assert np.array_equal(ri[own < 0], ui[own < 0])
+    # ghosts untouched; rescaling twice changes nothing more than rounding
+    assert np.array_equal(ur[0], u[0]) and np.array_equal(ur[..., -1], u[..., -1])
+    assert np.abs(orc.rescale(n, ur, cs, 3.0, own) - ur).max() < 1e-15
+
+
+def test_init_u_values(orc):
+    n = (9, 8, 7, 2)
+    seeds = _centres([(2.0, 3.0, 1.0, 0), (6.0, 5.0, 4.0, 1)])
+    u = orc.init_u(n, seeds, 1.0, 0.0)
+    assert u[1, 2, 4, 3] == 1.0                       # the seed voxel: 1/v
+    assert abs(u[1, 2, 4 + 4, 3 + 3] - 1.0 / 6.0) < 1e-16   # distance 5
+    assert u[0].max() == 0 and u[-1].max() == 0 and u[..., 0].max() == 0
+    uR = orc.init_u(n, seeds, 1.0, 3.0)
+    assert uR[1, 2, 4, 3] == 1.0 - 0.25
+    assert uR[1, 2, 4 + 4, 3 + 3] == 0.0              # beyond R
+    assert uR[2, 5, 6, 7] == 1.0 - 0.25               # second frame's own seed
+
+
+# -------------------------------------------------------------- assembly
+
+
+def _step_inputs(orc, n, seed, Gmin=0.05):
+    rng = np.random.default_rng(seed)
+    G = rng.uniform(Gmin, 1.0, size=(4,) + orc.padded_shape(n))
+    w = rand_padded(rng, n)
+    w[0] = w[-1] = 0
+    w[:, 0] = w[:, -1] = 0
+    w[:, :, 0] = w[:, :, -1] = 0
+    w[..., 0] = w[..., -1] = 0
+    return G, w
+
+
+def test_constant_preserved(orc):
+    n = (6, 5, 4, 3)
+    rng = np.random.default_rng(2)
+    G = rng.uniform(0.1, 1.0, size=(4,) + orc.padded_shape(n))
+    w = np.full(orc.padded_shape(n), 0.625)
+    coef, b = orc.assemble(n, G, w, 1.0, 1e-3, 0.5)
+    u, it, rr, st = orc.sor(n, coef, b, w, 1.5, 1e-12)
+    assert it == 0 and st == 0
+    assert np.abs(u - 0.625).max() < 1e-14
+
+
+def test_coefficients_symmetric_after_row_scaling(orc):
+    """c on a face = Abar of the owning cell times a face quantity (Sec. 3.2.2),
+    so around every plaquette P, P+e_d, P+e_d+e_e, P+e_e the product of the
+    ratios c(P->Q)/c(Q->P) is 1."""
+    n = (6, 5, 5, 4)
+    G, w = _step_inputs(orc, n, 4)
+    coef, b = orc.assemble(n, G, w, 0.8, 0.05, 0.3)
+    C = coef  # (t,z,y,x,8)
+    ax = {0: 3, 1: 2, 2: 1, 3: 0}
+
+    def ratio(P, d):
+        Q = list(P)
+        Q[ax[d]] += 1
+        return C[tuple(P) + (2 * d + 1,)] / C[tuple(Q) + (2 * d,)]
+
+    worst = 0.0
+    for d, e in itertools.combinations(range(4), 2):
+        for P in itertools.product(*[range(s - 1) for s in C.shape[:4]]):
+            Pd = list(P); Pd[ax[d]] += 1
+            Pe = list(P); Pe[ax[e]] += 1
+            loop = ratio(P, d) * ratio(Pd, e) / (ratio(Pe, d) * ratio(P, e))
+            worst = max(worst, abs(loop - 1.0))
+    assert worst < 1e-12
+
+
+def test_m_matrix_and_inverse_bound(orc):
+    """Stability section (Sec. 3.3): positive diagonal, non-positive off-diagonal,
+    strict diagonal dominance with margin >= 1, hence ||A^-1||_inf <= 1."""
+    n = (4, 3, 3, 2)
+    G, w = _step_inputs(orc, n, 5)
+    for tau in (1e-3, 0.5, 10.0, 1e6):
+        coef, b = orc.assemble(n, G, w, 1.0, 1e-3, tau)
+        A, _ = orc.dense_system(n, coef, b)
+        off = A - np.diag(np.diag(A))
+        assert (np.diag(A) > 0).all() and (off <= 0).all()
+        assert (np.diag(A) - np.abs(off).sum(1) >= 1 - 1e-9 * np.diag(A)).all()
+        assert np.abs(np.linalg.inv(A)).sum(1).max() <= 1 + 1e-9
+
+
+@pytest.mark.parametrize("n", [(3, 3, 2, 2), (4, 3, 3, 2), (5, 4, 2, 3)])
+def test_sor_matches_dense_lu(orc, n):
+    G, w = _step_inputs(orc, n, sum(n))
+    coef, b = orc.assemble(n, G, w, 1.0, 1e-2, 0.5)
+    A, bb = orc.dense_system(n, coef, b)
+    x = np.linalg.solve(A, bb).reshape(orc.interior_shape(n))
+    for order in (orc.LEX, orc.RB):
+        u, it, rr, st = orc.sor(n, coef, b, w, 1.4, 1e-15, 20000, order)
+        assert st == 0
+        assert np.abs(orc.interior(u) - x).max() < 1e-12
+
+
+def test_lex_and_rb_same_fixed_point(orc):
+    n = (8, 7, 6, 4)
+    G, w = _step_inputs(orc, n, 9)
+    coef, b = orc.assemble(n, G, w, 1.0, 1e-3, 0.5)
+    ul, _, rl, _ = orc.sor(n, coef, b, w, 1.5, 1e-13, 20000, orc.LEX)
+    ur, _, rr, _ = orc.sor(n, coef, b, w, 1.5, 1e-13, 20000, orc.RB)
+    assert np.abs(ul - ur).max() < 1e-11
+
+
+@pytest.mark.parametrize("tau", [1e-3, 0.5, 10.0, 1e6])
+def test_discrete_maximum_principle(orc, tau):
+    """min(u^D, min b) <= u^n <= max(u^D, max b) with u^D = 0 (the paper's
+    min-max principle with the Dirichlet data included), for any tau."""
+    n = (7, 6, 5, 4)
+    G, w = _step_inputs(orc, n, 21)
+    coef, b = orc.assemble(n, G, w, 1.0, 1e-3, tau)
+    u, it, rr, st = orc.sor(n, coef, b, w, 1.5, 1e-13, 100000, orc.RB)
+    ui = orc.interior(u)
+    assert ui.min() >= min(0.0, b.min()) - 1e-10
+    assert ui.max() <= max(0.0, b.max()) + 1e-10
+
+
+def test_axis_permutation_equivariance(orc):
+    """The scheme treats the four axes alike (uniform h): permuting the axes of
+    every input permutes the solution (24 permutations, red-black order)."""
+    n = (5, 4, 3, 3)
+    G, w = _step_inputs(orc, n, 17)
+    coef, b = orc.assemble(n, G, w, 1.0, 1e-2, 0.5)
+    ref, _, _, _ = orc.sor(n, coef, b, w, 1.3, 0.0, 25, orc.RB)
+    for perm in itertools.permutations(range(4)):
+        # perm[a] = old axis that becomes new axis a (axes in x,y,z,t order)
+        n2 = tuple(n[perm[a]] for a in range(4))
+        arr_axes = [3 - perm[3 - q] for q in range(4)]   # numpy axes (t,z,y,x)
+        G2 = np.stack([np.transpose(G[perm[a]], arr_axes) for a in range(4)])
+        w2 = np.ascontiguousarray(np.transpose(w, arr_axes))
+        c2, b2 = orc.assemble(n2, G2, w2, 1.0, 1e-2, 0.5)
+        u2, _, _, _ = orc.sor(n2, c2, b2, w2, 1.3, 0.0, 25, orc.RB)
+        assert np.abs(u2 - np.transpose(ref, arr_axes)).max() < 1e-13, perm
+
+
+def test_step_pipeline_dmp_and_rescale(orc):
+    """A whole step on the config-1 style input stays in [0,1] after rescaling."""
+    import synth
+
+    img = synth.spheres_cfg1(n=(14, 14, 14, 3), n_spheres=1)
+    pp = orc.PrepareParams(ball_r=5.0)
+    sp = orc.StepParams(ball_r=5.0)
+    out = orc.run(img.n, img.image, img.centres, img.seeds, pp, sp, steps=2)
+    for rec in out["steps"]:
+        assert rec["status"] == 0 and rec["rel_res"] <= 1e-8
+        assert rec["u_resc"].min() >= -1e-9 and rec["u_resc"].max() <= 1 + 1e-9
+
+
+# ------------------------------------------------------------------- EOC
+
+
+def _table():
+    with open(os.path.join(HERE, "golden", "eoc_table.json")) as f:
+        return json.load(f)["rows"]
+
+
+def test_eoc_second_order(orc):
+    """Sec. 3.4 convergence test at n=10 (1 step) and n=20 (4 steps): the
+    scheme converges at (at least) second order and its errors do not exceed
+    the paper's table.  The printed digits themselves are not reproduced: the
+    paper does not state its grid placement / boundary data, and the reading
+    used here (cell-centred grid, exact Dirichlet ghosts) is more accurate."""
+    rows = _table()
+    e10, _ = orc.eoc_run(10, 1)
+    e20, _ = orc.eoc_run(20, 4)
+    assert e10 <= rows[0]["error"] and e20 <= rows[1]["error"]
+    assert np.log2(e10 / e20) >= 1.8
+
+
+@pytest.mark.slow
+def test_eoc_n40(orc):
+    rows = _table()
+    e20, _ = orc.eoc_run(20, 4)
+    e40, _ = orc.eoc_run(40, 16)
+    assert e40 <= rows[2]["error"]
+    assert np.log2(e20 / e40) >= 1.8
+
+
+# ------------------------------------------------------- additional pins
+
+
+def test_threshold_tie_goes_to_beta(orc):
+    """The thresholded image takes beta where I0 >= TH (Sec. 3.1, '>=' as printed):
+    with values {0, 0.5, 1} and lambda = 1/2 the cells equal to TH = 0.5 become beta."""
+    n = (9, 9, 9, 1)
+    I0 = np.zeros(orc.interior_shape(n))
+    I0[0, 4, 4, 4] = 1.0
+    I0[0, 4, 4, 5] = 0.5
+    cs = _centres([(4.0, 4.0, 4.0, 0)])
+    own = orc.owner_map(n, cs, 3.0)
+    ITH = orc.threshold(n, I0, cs, 3.0, 0.5, own)
+    assert ITH[0, 4, 4, 5] == 1.0 and ITH[0, 4, 4, 4] == 1.0 and ITH[0, 4, 4, 3] == 0.0
+
+
+@pytest.mark.parametrize("gamma", [1.0, 0.3])
+def test_large_eps_is_linear_heat_step(orc, gamma):
+    """For eps >> |grad u| the coefficients tend to tau/h^2 * G (A = Abar = eps),
+    so with G = gamma the step is the implicit Dirichlet heat step; the discrete
+    sine mode sin(pi m i/(N+1)) is divided by 1 + tau*gamma*(4/h^2) sin^2(pi m/(2(N+1)))."""
+    n = (7, 6, 5, 4)
+    h, tau = 0.5, 0.05
+    G = np.full((4,) + orc.padded_shape(n), gamma)
+    idx = np.indices(orc.padded_shape(n)).astype(float)       # t,z,y,x
+    modes = (1, 2, 1, 1)                                          # x,y,z,t
+    w = np.ones(orc.padded_shape(n))
+    lam = 0.0
+    for a in range(4):
+        N = n[a]
+        w = w * np.sin(np.pi * modes[a] * idx[3 - a] / (N + 1))
+        lam += (4.0 / h ** 2) * np.sin(np.pi * modes[a] / (2 * (N + 1))) ** 2
+    w[0] = w[-1] = 0; w[:, 0] = w[:, -1] = 0; w[:, :, 0] = w[:, :, -1] = 0; w[..., 0] = w[..., -1] = 0
+    coef, b = orc.assemble(n, G, w, h, 1e8, tau)
+    u, it, rr, st = orc.sor(n, coef, b, w, 1.5, 1e-14, 10000)
+    assert np.abs(orc.interior(u) - orc.interior(w) / (1 + tau * gamma * lam)).max() < 1e-12
+
+
+def test_sor_rate_matches_young_theory(orc):
+    """Red-black ordering makes the matrix consistently ordered with a real
+    Jacobi spectrum (it is a diagonal times a symmetric matrix), so for
+    omega >= omega_b = 2/(1+sqrt(1-rho_J^2)) the SOR error contracts by exactly
+    omega-1 per iteration asymptotically (Young's theorem)."""
+    n = (4, 4, 3, 3)
+    G, w = _step_inputs(orc, n, 31)
+    coef, b = orc.assemble(n, G, w, 1.0, 1e-3, 50.0)
+    A, bb = orc.dense_system(n, coef, b)
+    x = np.linalg.solve(A, bb).reshape(orc.interior_shape(n))
+    Dg = np.diag(A)
+    rhoJ = np.abs(np.linalg.eigvals(np.eye(len(Dg)) - A / Dg[:, None])).max()
+    omega_b = 2.0 / (1.0 + np.sqrt(1.0 - rhoJ ** 2))
+    omega = min(1.98, omega_b + 0.5 * (2.0 - omega_b))
+    ks = np.arange(10, 42, 2)
+    errs = []
+    for k in ks:
+        u, *_ = orc.sor(n, coef, b, w, omega, 0.0, int(k), orc.RB)
+        errs.append(np.abs(orc.interior(u) - x).max())
+    rate = np.exp(np.polyfit(ks, np.log(errs), 1)[0])       # errors stay far above rounding
+    assert abs(rate - (omega - 1.0)) < 0.03 * (omega - 1.0), (rate, omega, rhoJ)
