@@ -1,0 +1,242 @@
+/*
+ * subsurf4d.h -- C ABI of the MI355X (gfx950) library for the semi-implicit
+ * time step of the 4D generalized subjective-surface (SUBSURF) segmentation
+ * model of Uba, Mikula and Park, "4D Segmentation Algorithm with application
+ * to 3D+time Image Segmentation" (arXiv 2111.11866).
+ *
+ * Problem (Sec. 3.1): given a 4D image I0 on a box of N1 x N2 x N3 voxels and
+ * N4 frames, per-frame centres c_m^l of the objects, and parameters, evolve
+ *     u_t = |grad u| div(G0 grad u / |grad u|),  u = 0 on the boundary,
+ * with G0 = g(delta |grad I0_sigma| + vartheta |grad ITH_sigma|), g(s) = 1/(1+K s^2).
+ * Each time step (Sec. 3.2) assembles a 9-point 4D finite-volume system from
+ * reduced-diamond-cell face gradients of the previous, locally rescaled
+ * solution and solves it by red-black SOR (Sec. 3.2.2), then rescales u to
+ * [0,1] in balls around the centres (local rescaling remark, Sec. 3.2.2).
+ *
+ * Conventions shared by every entry point
+ *  - Grid: interior sizes n[0..3] = (N1 x, N2 y, N3 z, N4 t), uniform spacing h.
+ *  - "padded" arrays have (N1+2)(N2+2)(N3+2)(N4+2) entries, x fastest
+ *    (index ((l*(N3+2)+k)*(N2+2)+j)*(N1+2)+i, 0 <= i <= N1+1 ...); index 0 and
+ *    N+1 along each axis are the boundary (ghost) layer that holds the
+ *    Dirichlet data u^D (Sec. 3.7 layout).  "interior" arrays have N1 N2 N3 N4
+ *    entries, x fastest.
+ *  - Voxel coordinates of interior cell (i,j,k,l) are X = (i-1, j-1, k-1) in
+ *    frame l-1; centres use the same coordinates.
+ *  - Every pointer argument named "device" is device memory on the current
+ *    HIP device; every other pointer is host memory.  The caller owns all
+ *    memory.  The library never allocates or frees device memory in these
+ *    calls; scratch space comes from the caller's workspace.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
+ *    it.  Calls that iterate to a tolerance (prepare, step, solve) read the
+ *    device-side convergence state between chunks of iterations and therefore
+ *    synchronise `stream`; when they return, every result they write is final.
+ *  - Errors: argument and shape checks happen before anything is enqueued and
+ *    return a negative status.  A HIP failure returns SUBSURF4D_EDEVICE.  No
+ *    C++ exception crosses this interface.  subsurf4d_last_error() gives a
+ *    thread-local message for the last failing call on the calling thread.
+ */
+#ifndef SUBSURF4D_H
+#define SUBSURF4D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+enum {
+    SUBSURF4D_OK = 0,
+    SUBSURF4D_NOT_CONVERGED = 1,  /* max_iter reached; last iterate returned   */
+    SUBSURF4D_EINVAL = -1,        /* NULL pointer or parameter out of range     */
+    SUBSURF4D_ESHAPE = -2,        /* grid sizes not supported                   */
+    SUBSURF4D_EWORKSPACE = -3,    /* workspace smaller than *_workspace_bytes   */
+    SUBSURF4D_ENONFINITE = -4,    /* a residual or norm became NaN/Inf          */
+    SUBSURF4D_EDEVICE = -5        /* a HIP call failed                          */
+};
+
+/* image element types */
+enum { SUBSURF4D_U8 = 0, SUBSURF4D_F32 = 1, SUBSURF4D_F64 = 2 };
+
+/* arithmetic of the solve: FP64 throughout, or FP32/BF16 sweeps refined in FP64 */
+enum { SUBSURF4D_FP64 = 0, SUBSURF4D_MIXED = 1 };
+
+typedef struct {
+    int32_t n[4];   /* interior sizes (x, y, z, t); each >= 1 */
+    double h;       /* uniform grid spacing (> 0) */
+} subsurf4d_grid;
+
+/* A ball centre / seed: voxel coordinates and 0-based frame (16 bytes). */
+typedef struct {
+    float x, y, z;
+    int32_t frame;
+} subsurf4d_centre;
+
+/* Parameters of the per-job preparation (Sec. 3.1, Sec. 3.2.2 G equation). */
+typedef struct {
+    double K;             /* edge-detector sensitivity, g(s) = 1/(1+K s^2), K >= 0 */
+    double delta;         /* weight of |grad I0_sigma| */
+    double vartheta;      /* weight of |grad ITH_sigma| */
+    double lambda;        /* threshold TH = lambda*alpha + (1-lambda)*beta, in [0,1] */
+    double ball_r;        /* ball radius r (voxels) of the local thresholding */
+    double smooth_tau;    /* presmoothing: implicit heat-step size (>= 0) */
+    int32_t smooth_steps; /* number of implicit heat steps (>= 0) */
+    int32_t smooth_max_iter; /* SOR iteration cap of each heat step */
+    double smooth_omega;  /* SOR relaxation of the heat steps, in (0,2) */
+    double smooth_tol;    /* relative L2 residual tolerance of the heat steps */
+    double image_scale;   /* I0 = image_scale * image[...] */
+} subsurf4d_prepare_params;
+
+/* Parameters of one time step (Sec. 3.2). */
+typedef struct {
+    double eps;           /* regularisation epsilon of A_eps (> 0) */
+    double tau;           /* time step (>= 0; 0 gives the identity solve) */
+    double omega;         /* SOR relaxation, in (0,2) */
+    double tol;           /* stop at ||b - A u||_2 <= tol ||b||_2 (relative L2) */
+    int32_t max_iter;     /* iteration cap (>= 1) */
+    int32_t check_every;  /* test the stopping rule every this many iterations (>= 1) */
+    int32_t rescale;      /* 1: local rescaling after the solve (needs owner/centres) */
+    int32_t precision;    /* SUBSURF4D_FP64 or SUBSURF4D_MIXED */
+    double ball_r;        /* ball radius of the local rescaling */
+    double refine_tol;    /* MIXED: FP64 relative residual target of refinement */
+    int32_t inner_sweeps; /* MIXED: FP32 red-black iterations per refinement pass */
+    int32_t fixed_iters;  /* > 0: run exactly this many iterations (tol ignored) */
+    int32_t iter_hint;    /* expected iteration count (0 = unknown); only sizes launch chunks */
+    int32_t reserved;
+} subsurf4d_step_params;
+
+/* Outcome of a solve.  Iterations are full red-black iterations. */
+typedef struct {
+    int32_t status;           /* SUBSURF4D_OK, _NOT_CONVERGED or _ENONFINITE */
+    int32_t iterations;       /* k of the returned iterate u^(k) (total inner sweeps for MIXED) */
+    int32_t outer_iterations; /* MIXED: refinement passes; FP64: 0 */
+    int32_t reserved;
+    double rel_residual;      /* ||b - A u||_2 / ||b||_2 of the returned iterate */
+    double bnorm;             /* ||b||_2 */
+} subsurf4d_result;
+
+/* Bytes of device workspace the calls below need for this grid, for
+ * `n_centres` ball centres, in the given precision.  Host-only; 0 if the grid
+ * is invalid.  One workspace serves every call on the grid (not concurrently). */
+size_t subsurf4d_workspace_bytes(const subsurf4d_grid* grid, int32_t n_centres, int32_t precision);
+
+/*
+ * Per-job preparation (Sec. 3.1 local thresholding and presmoothing,
+ * Sec. 3.2.2 edge detector on faces):
+ *  - owner (device, interior int32): index of the ball B(c_m^l, r) of the cell's
+ *    frame that contains the cell, nearest centre first, ties to the lowest
+ *    index; -1 if none.  Balls are |X - c| <= r in voxel units.
+ *  - I^TH = beta_m where I0 >= lambda*alpha_m + (1-lambda)*beta_m, else alpha_m,
+ *    with alpha_m/beta_m the min/max of I0 over ball m, on owned cells;
+ *    I^TH = I0 elsewhere.
+ *  - I0 and I^TH are each smoothed by `smooth_steps` implicit steps of the
+ *    zero-Neumann heat equation, solved by red-black SOR to smooth_tol.
+ *  - G (device, 4 x padded doubles, G[d*padded + p]): g on the face between
+ *    cell p and p+e_d (d = 0..3 for x,y,z,t), from reduced-diamond-cell
+ *    gradients of the smoothed images; image values outside the interior are
+ *    copies of the nearest interior value.
+ * image (device): interior array of `image_dtype`.  centres (device):
+ * n_centres entries (0 allowed).  Returns SUBSURF4D_NOT_CONVERGED if a heat
+ * step hit smooth_max_iter (G is still written).
+ */
+int subsurf4d_prepare_g(const subsurf4d_grid* grid, const void* image, int32_t image_dtype,
+                        const subsurf4d_centre* centres, int32_t n_centres,
+                        const subsurf4d_prepare_params* params, double* G, int32_t* owner,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Initial segmentation function (Sec. 2 peak profile, applied per frame as
+ * Sec. 3.1 states): for every interior cell, the maximum over the seeds of
+ * its own frame of 1/(|X - s| + v) (R <= 0), or of max(0, 1/(|X-s|+v) - 1/(R+v))
+ * (R > 0: profile cut at radius R and shifted for zero Dirichlet data).
+ * Cells of frames without a seed get 0.  Ghost cells of u (device, padded)
+ * are set to 0.  With R <= 0 the cost is O(cells x seeds).
+ */
+int subsurf4d_init_u(const subsurf4d_grid* grid, const subsurf4d_centre* seeds, int32_t n_seeds,
+                     double v, double R, double* u, void* stream);
+
+/*
+ * Local rescaling (Sec. 3.2.2 remark): for each ball m, mu_m/xi_m = min/max of
+ * u over the ball; every cell with owner == m becomes (u - mu_m)/(xi_m - mu_m)
+ * unless xi_m - mu_m < 1e-12.  u (device, padded) is rescaled in place; ghosts
+ * and cells without an owner are unchanged.  Needs the workspace for the
+ * per-ball extrema.
+ */
+int subsurf4d_rescale(const subsurf4d_grid* grid, const subsurf4d_centre* centres,
+                      int32_t n_centres, double ball_r, const int32_t* owner, double* u,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Coefficients of one step's system, exported in the natural layout (for
+ * inspection and tests; subsurf4d_step assembles internally):
+ *   c_f = tau/h^2 * Abar_P * G_f / A_f on the 8 faces f of cell P, face order
+ *   -x,+x,-y,+y,-z,+z,-t,+t; A_f = sqrt(eps^2 + |grad_f u|^2),
+ *   Abar_P = sqrt(eps^2 + (1/8) sum_f |grad_f u|^2) (Sec. 3.2.2, uniform-h system);
+ *   b_P = u_P + sum over ghost neighbours of c_f * u^D.
+ * u (device, padded) is u^{resc;n-1} with Dirichlet data in its ghosts.
+ * coef (device, interior x 8 doubles, cell-major), b (device, interior).
+ */
+int subsurf4d_assemble(const subsurf4d_grid* grid, const double* G, const double* u,
+                       const subsurf4d_step_params* params, double* coef, double* b,
+                       void* stream);
+
+/*
+ * One semi-implicit time step (Sec. 3.2 and the implementation overview of
+ * Sec. 3.5): assemble the system from u = u^{resc;n-1} (device, padded) and G,
+ * solve it by red-black SOR (cells with i+j+k+l even first), starting from
+ * u^{resc;n-1}, with the stopping rule: R_k = ||b - A u^(k)||_2 over interior
+ * rows; test k = 0 and then every check_every-th iteration; stop at the first
+ * R_k <= tol ||b||_2 and return u^(k); after max_iter iterations return
+ * u^(max_iter) with SUBSURF4D_NOT_CONVERGED.  Then, if params->rescale, apply
+ * the local rescaling with (centres, owner).  u is overwritten with the new
+ * level (ghosts unchanged).  result (host) receives the outcome.
+ * precision MIXED: FP32 red-black sweeps on BF16-stored coefficients inside
+ * an FP64 iterative refinement to refine_tol (the FP64 residual uses the FP64
+ * operator).
+ */
+int subsurf4d_step(const subsurf4d_grid* grid, const double* G, const subsurf4d_centre* centres,
+                   int32_t n_centres, const int32_t* owner, double* u,
+                   const subsurf4d_step_params* params, subsurf4d_result* result,
+                   void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * The linear solve alone (Sec. 3.2.2 red-black SOR) for externally given
+ * coefficients: coef (device, interior x 8, face order as above), b (device,
+ * interior; Dirichlet terms already included), u (device, padded; interior =
+ * initial guess, overwritten by the result; ghosts ignored).  The diagonal is
+ * 1 + sum of the 8 coefficients; neighbours outside the interior do not
+ * enter.  Same stopping rule and result as subsurf4d_step.
+ */
+int subsurf4d_solve(const subsurf4d_grid* grid, const double* coef, const double* b, double* u,
+                    const subsurf4d_step_params* params, subsurf4d_result* result,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* Static text for a status code. */
+const char* subsurf4d_status_string(int status);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* subsurf4d_last_error(void);
+
+/* Library version string. */
+const char* subsurf4d_version(void);
+
+/*
+ * Benchmark instrumentation of the red-black sweeps.  When enabled, every
+ * solve records HIP events around each launch chunk of sweeps on its own
+ * stream (one extra event pair per chunk; the chunk is synchronised anyway)
+ * and adds: the chunks' elapsed milliseconds, the number of sweep launches
+ * that did work (2K+1 for a solve returning iterate K: the extra red
+ * half-sweep tests the stopping rule), the voxel updates K x interior cells,
+ * and one solve.  op: 0 disable, 1 enable, 2 reset the totals, 3 read only.
+ * Every call writes the current totals to the non-NULL outputs (host memory).
+ * Process-wide, thread-safe.
+ */
+void subsurf4d_timing(int32_t op, double* sweep_ms, int64_t* sweep_launches, int64_t* voxel_updates,
+                      int64_t* solves);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SUBSURF4D_H */

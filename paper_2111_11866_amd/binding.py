@@ -1,0 +1,286 @@
+"""ctypes binding of libsubsurf4d.so (argument marshalling only).
+
+Every numerical step runs in the HIP library; this module only passes device
+pointers of torch tensors, the current HIP stream and parameter structs, and
+turns negative status codes into exceptions.  If the library has not been
+built, importing works but every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libsubsurf4d.so")
+
+OK, NOT_CONVERGED = 0, 1
+EINVAL, ESHAPE, EWORKSPACE, ENONFINITE, EDEVICE = -1, -2, -3, -4, -5
+U8, F32, F64 = 0, 1, 2
+FP64, MIXED = 0, 1
+
+CENTRE_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("z", "<f4"), ("frame", "<i4")])
+
+EXPORTED = (
+    "subsurf4d_workspace_bytes", "subsurf4d_prepare_g", "subsurf4d_init_u", "subsurf4d_rescale",
+    "subsurf4d_assemble", "subsurf4d_step", "subsurf4d_solve", "subsurf4d_status_string",
+    "subsurf4d_last_error", "subsurf4d_version", "subsurf4d_timing",
+)
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 4), ("h", ctypes.c_double)]
+
+
+class PrepareParamsC(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_double), ("delta", ctypes.c_double), ("vartheta", ctypes.c_double),
+                ("lam", ctypes.c_double), ("ball_r", ctypes.c_double), ("smooth_tau", ctypes.c_double),
+                ("smooth_steps", ctypes.c_int32), ("smooth_max_iter", ctypes.c_int32),
+                ("smooth_omega", ctypes.c_double), ("smooth_tol", ctypes.c_double),
+                ("image_scale", ctypes.c_double)]
+
+
+class StepParamsC(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("tau", ctypes.c_double), ("omega", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("rescale", ctypes.c_int32), ("precision", ctypes.c_int32), ("ball_r", ctypes.c_double),
+                ("refine_tol", ctypes.c_double), ("inner_sweeps", ctypes.c_int32),
+                ("fixed_iters", ctypes.c_int32), ("iter_hint", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("outer_iterations", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("bnorm", ctypes.c_double)]
+
+    def as_dict(self):
+        return dict(status=self.status, iterations=self.iterations, outer=self.outer_iterations,
+                    rel_res=self.rel_residual, bnorm=self.bnorm)
+
+
+@dataclass(frozen=True)
+class PrepareParams:
+    K: float = 1000.0
+    delta: float = 0.5
+    vartheta: float = 0.5
+    lam: float = 0.5
+    ball_r: float = 8.0
+    smooth_tau: float = 0.1
+    smooth_steps: int = 1
+    smooth_max_iter: int = 10000
+    smooth_omega: float = 1.5
+    smooth_tol: float = 1e-13
+    image_scale: float = 1.0
+
+    def c(self) -> PrepareParamsC:
+        return PrepareParamsC(self.K, self.delta, self.vartheta, self.lam, self.ball_r, self.smooth_tau,
+                              self.smooth_steps, self.smooth_max_iter, self.smooth_omega, self.smooth_tol,
+                              self.image_scale)
+
+
+@dataclass(frozen=True)
+class StepParams:
+    eps: float = 1e-3
+    tau: float = 0.5
+    omega: float = 1.5
+    tol: float = 1e-8
+    max_iter: int = 10000
+    check_every: int = 1
+    rescale: bool = True
+    precision: int = FP64
+    ball_r: float = 8.0
+    refine_tol: float = 1e-10
+    inner_sweeps: int = 8
+    fixed_iters: int = 0
+    iter_hint: int = 0
+
+    def c(self) -> StepParamsC:
+        return StepParamsC(self.eps, self.tau, self.omega, self.tol, self.max_iter, self.check_every,
+                           int(bool(self.rescale)), self.precision, self.ball_r, self.refine_tol,
+                           self.inner_sweeps, self.fixed_iters, self.iter_hint, 0)
+
+
+class Subsurf4dError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"subsurf4d status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+        L.subsurf4d_workspace_bytes.argtypes = [ctypes.POINTER(Grid), I, I]
+        L.subsurf4d_workspace_bytes.restype = SZ
+        L.subsurf4d_prepare_g.argtypes = [ctypes.POINTER(Grid), P, I, P, I, ctypes.POINTER(PrepareParamsC),
+                                          P, P, P, SZ, P]
+        L.subsurf4d_init_u.argtypes = [ctypes.POINTER(Grid), P, I, D, D, P, P]
+        L.subsurf4d_rescale.argtypes = [ctypes.POINTER(Grid), P, I, D, P, P, P, SZ, P]
+        L.subsurf4d_assemble.argtypes = [ctypes.POINTER(Grid), P, P, ctypes.POINTER(StepParamsC), P, P, P]
+        L.subsurf4d_step.argtypes = [ctypes.POINTER(Grid), P, P, I, P, P, ctypes.POINTER(StepParamsC),
+                                     ctypes.POINTER(Result), P, SZ, P]
+        L.subsurf4d_solve.argtypes = [ctypes.POINTER(Grid), P, P, P, ctypes.POINTER(StepParamsC),
+                                      ctypes.POINTER(Result), P, SZ, P]
+        L.subsurf4d_status_string.argtypes = [ctypes.c_int]
+        L.subsurf4d_status_string.restype = ctypes.c_char_p
+        L.subsurf4d_last_error.restype = ctypes.c_char_p
+        L.subsurf4d_version.restype = ctypes.c_char_p
+        L.subsurf4d_timing.argtypes = [I, P, P, P, P]
+        L.subsurf4d_timing.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc < 0:
+        raise Subsurf4dError(rc, lib().subsurf4d_last_error().decode())
+    return rc
+
+
+def _p(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    assert t.is_contiguous(), "tensors passed to the library must be contiguous"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def grid(n, h=1.0) -> Grid:
+    return Grid((ctypes.c_int32 * 4)(*[int(v) for v in n]), float(h))
+
+
+def padded_shape(n):
+    n1, n2, n3, n4 = n
+    return (n4 + 2, n3 + 2, n2 + 2, n1 + 2)
+
+
+def interior_shape(n):
+    n1, n2, n3, n4 = n
+    return (n4, n3, n2, n1)
+
+
+def centres_tensor(centres, device="cuda"):
+    """Structured centre array (x, y, z float32, frame int32) -> device bytes."""
+    import torch
+
+    a = np.ascontiguousarray(np.asarray(centres, dtype=CENTRE_DTYPE))
+    if a.size == 0:
+        return torch.zeros(16, dtype=torch.uint8, device=device), 0
+    return torch.from_numpy(a.view(np.uint8).copy()).to(device), int(a.size)
+
+
+def workspace_bytes(n, n_centres=0, precision=FP64) -> int:
+    return int(lib().subsurf4d_workspace_bytes(ctypes.byref(grid(n)), int(n_centres), int(precision)))
+
+
+def alloc_workspace(n, n_centres=0, precision=FP64, device="cuda"):
+    import torch
+
+    nb = workspace_bytes(n, n_centres, precision)
+    if nb == 0:
+        raise Subsurf4dError(ESHAPE, "unsupported grid")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def prepare_g(n, h, image, centres, n_centres, params: PrepareParams, G, owner, ws, stream=None):
+    import torch
+
+    dt = {torch.uint8: U8, torch.float32: F32, torch.float64: F64}[image.dtype]
+    return _check(lib().subsurf4d_prepare_g(ctypes.byref(grid(n, h)), _p(image), dt, _p(centres),
+                                             int(n_centres), ctypes.byref(params.c()), _p(G), _p(owner),
+                                             _p(ws), ws.numel(), _stream(stream)))
+
+
+def init_u(n, h, seeds, n_seeds, v, R, u, stream=None):
+    return _check(lib().subsurf4d_init_u(ctypes.byref(grid(n, h)), _p(seeds), int(n_seeds), float(v),
+                                          float(R), _p(u), _stream(stream)))
+
+
+def rescale(n, h, centres, n_centres, ball_r, owner, u, ws, stream=None):
+    return _check(lib().subsurf4d_rescale(ctypes.byref(grid(n, h)), _p(centres), int(n_centres),
+                                           float(ball_r), _p(owner), _p(u), _p(ws), ws.numel(),
+                                           _stream(stream)))
+
+
+def assemble(n, h, G, u, params: StepParams, coef, b, stream=None):
+    return _check(lib().subsurf4d_assemble(ctypes.byref(grid(n, h)), _p(G), _p(u), ctypes.byref(params.c()),
+                                            _p(coef), _p(b), _stream(stream)))
+
+
+def step(n, h, G, centres, n_centres, owner, u, params: StepParams, ws, stream=None) -> dict:
+    res = Result()
+    _check(lib().subsurf4d_step(ctypes.byref(grid(n, h)), _p(G), _p(centres), int(n_centres), _p(owner),
+                                _p(u), ctypes.byref(params.c()), ctypes.byref(res), _p(ws), ws.numel(),
+                                _stream(stream)))
+    return res.as_dict()
+
+
+def solve(n, h, coef, b, u, params: StepParams, ws, stream=None) -> dict:
+    res = Result()
+    _check(lib().subsurf4d_solve(ctypes.byref(grid(n, h)), _p(coef), _p(b), _p(u), ctypes.byref(params.c()),
+                                 ctypes.byref(res), _p(ws), ws.numel(), _stream(stream)))
+    return res.as_dict()
+
+
+def timing(op: int = 3) -> dict:
+    """Sweep instrumentation: op 0 disable, 1 enable, 2 reset, 3 read."""
+    ms = ctypes.c_double(0.0)
+    la, up, so = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    lib().subsurf4d_timing(int(op), ctypes.byref(ms), ctypes.byref(la), ctypes.byref(up), ctypes.byref(so))
+    return dict(sweep_ms=ms.value, sweep_launches=la.value, voxel_updates=up.value, solves=so.value)
+
+
+def version() -> str:
+    return lib().subsurf4d_version().decode()
+
+
+class Job:
+    """Device-resident state of one segmentation job (image, G, owner map, u,
+    workspace), with the pipeline of the implementation overview (Sec. 3.5):
+    prepare -> initial function -> rescale -> steps.  Memory comes from torch."""
+
+    def __init__(self, n, image_np, centres, seeds, h=1.0, precision=FP64, device="cuda"):
+        import torch
+
+        self.n, self.h, self.device = tuple(int(v) for v in n), float(h), device
+        self.image = torch.from_numpy(np.ascontiguousarray(image_np)).to(device)
+        self.centres, self.nc = centres_tensor(centres, device)
+        self.seeds, self.ns = centres_tensor(seeds, device)
+        self.G = torch.empty((4,) + padded_shape(self.n), dtype=torch.float64, device=device)
+        self.owner = torch.empty(interior_shape(self.n), dtype=torch.int32, device=device)
+        self.u = torch.empty(padded_shape(self.n), dtype=torch.float64, device=device)
+        self.ws = alloc_workspace(self.n, self.nc, precision, device)
+        self.last_iters = 0
+
+    def prepare(self, pp: PrepareParams):
+        return prepare_g(self.n, self.h, self.image, self.centres, self.nc, pp, self.G, self.owner, self.ws)
+
+    def init(self, v=1.0, R=0.0, ball_r=8.0, do_rescale=True):
+        init_u(self.n, self.h, self.seeds, self.ns, v, R, self.u)
+        if do_rescale:
+            rescale(self.n, self.h, self.centres, self.nc, ball_r, self.owner, self.u, self.ws)
+
+    def step(self, sp: StepParams):
+        from dataclasses import replace
+
+        if sp.iter_hint == 0 and self.last_iters:
+            sp = replace(sp, iter_hint=self.last_iters)
+        r = step(self.n, self.h, self.G, self.centres, self.nc, self.owner, self.u, sp, self.ws)
+        self.last_iters = r["iterations"]
+        return r

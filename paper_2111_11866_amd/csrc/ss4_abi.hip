@@ -1,0 +1,312 @@
+// extern "C" entry points of libsubsurf4d.so: argument checks, workspace
+// planning and dispatch to the launchers.  No C++ exception crosses this file.
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <mutex>
+#include <string>
+
+#include "ss4_internal.hpp"
+
+namespace ss4 {
+
+namespace {
+thread_local std::string g_error;
+std::mutex g_timing_mu;
+bool g_timing_on = false;
+TimingTotals g_timing;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+bool timing_enabled()
+{
+    std::lock_guard<std::mutex> g(g_timing_mu);
+    return g_timing_on;
+}
+
+void timing_add(double ms, int64_t launches, int64_t updates)
+{
+    std::lock_guard<std::mutex> g(g_timing_mu);
+    g_timing.sweep_ms += ms;
+    g_timing.sweep_launches += launches;
+    g_timing.voxel_updates += updates;
+    g_timing.solves += 1;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    g_error = std::string(what) + ": " + hipGetErrorString(e);
+    return SUBSURF4D_EDEVICE;
+}
+
+bool plan_workspace(const int32_t n[4], int32_t n_centres, int32_t precision, WsPlan* P)
+{
+    for (int d = 0; d < 4; ++d)
+        if (n[d] < 1 || n[d] > (1 << 20)) return false;
+    const Layout L = make_layout(n);
+    if (L.npad > ((int64_t)1 << 40)) return false;
+    P->L = L;
+    P->n_centres = n_centres;
+    P->precision = precision;
+    size_t off = 0;
+    P->ctrl = off; off += align256(sizeof(Ctrl));
+    P->part_a = off; off += align256(sizeof(double) * kGridCap);
+    P->part_b = off; off += align256(sizeof(double) * kGridCap);
+    P->balls = off; off += align256(sizeof(double) * 2 * (size_t)(n_centres > 0 ? n_centres : 1));
+    P->big = off;
+
+    size_t s = off;
+    P->ured0 = s; s += align256(sizeof(double) * L.usplit);
+    P->ured1 = s; s += align256(sizeof(double) * L.usplit);
+    P->ublack = s; s += align256(sizeof(double) * L.usplit);
+    P->coef = s; s += align256(sizeof(double) * 16 * L.csplit);
+    P->rhs = s; s += align256(sizeof(double) * 2 * L.csplit);
+    if (precision == SUBSURF4D_MIXED) {
+        P->xf64 = s; s += align256(sizeof(double) * L.npad);          // FP64 iterate (padded)
+        P->rf32 = s; s += align256(sizeof(float) * 2 * L.csplit);     // FP32 residual, split
+        P->dred0 = s; s += align256(sizeof(float) * L.usplit);        // FP32 correction, split
+        P->dred1 = s; s += align256(sizeof(float) * L.usplit);
+        P->dblack = s; s += align256(sizeof(float) * L.usplit);
+        P->coef16 = s; s += align256(sizeof(uint16_t) * 16 * L.csplit);
+        P->rhs32 = s; s += align256(sizeof(float) * 2 * L.csplit);
+    }
+    P->step_bytes = s - off;
+
+    size_t q = off;
+    P->I0 = q; q += align256(sizeof(double) * L.nint);
+    P->ITH = q; q += align256(sizeof(double) * L.nint);
+    P->S0 = q; q += align256(sizeof(double) * L.nint);
+    P->S1 = q; q += align256(sizeof(double) * L.nint);
+    P->prep_bytes = q - off;
+
+    P->total = off + (P->step_bytes > P->prep_bytes ? P->step_bytes : P->prep_bytes);
+    return true;
+}
+
+}  // namespace ss4
+
+using namespace ss4;
+
+static_assert(sizeof(subsurf4d_grid) == 24, "grid layout");
+static_assert(sizeof(subsurf4d_centre) == 16, "centre layout");
+static_assert(sizeof(subsurf4d_prepare_params) == 80, "prepare params layout");
+static_assert(sizeof(subsurf4d_step_params) == 80, "step params layout");
+static_assert(sizeof(subsurf4d_result) == 32, "result layout");
+
+namespace {
+
+int fail(int code, const char* msg)
+{
+    set_error(msg);
+    return code;
+}
+
+int check_grid(const subsurf4d_grid* g)
+{
+    if (!g) return fail(SUBSURF4D_EINVAL, "grid is NULL");
+    for (int d = 0; d < 4; ++d)
+        if (g->n[d] < 1 || g->n[d] > (1 << 20)) return fail(SUBSURF4D_ESHAPE, "grid size out of range");
+    if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(SUBSURF4D_EINVAL, "h must be positive and finite");
+    return 0;
+}
+
+int check_ws(const WsPlan& P, void* ws, size_t bytes)
+{
+    if (!ws) return fail(SUBSURF4D_EINVAL, "workspace is NULL");
+    if (bytes < P.total) return fail(SUBSURF4D_EWORKSPACE, "workspace too small (see subsurf4d_workspace_bytes)");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(SUBSURF4D_EINVAL, "workspace must be 256-byte aligned");
+    return 0;
+}
+
+int check_step_params(const subsurf4d_step_params* p)
+{
+    if (!p) return fail(SUBSURF4D_EINVAL, "params is NULL");
+    if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(SUBSURF4D_EINVAL, "eps must be positive");
+    if (!(p->tau >= 0.0) || !std::isfinite(p->tau)) return fail(SUBSURF4D_EINVAL, "tau must be >= 0");
+    if (!(p->omega > 0.0 && p->omega < 2.0)) return fail(SUBSURF4D_EINVAL, "omega must be in (0,2)");
+    if (!(p->tol >= 0.0)) return fail(SUBSURF4D_EINVAL, "tol must be >= 0");
+    if (p->fixed_iters <= 0 && p->max_iter < 1) return fail(SUBSURF4D_EINVAL, "max_iter must be >= 1");
+    if (p->check_every < 0) return fail(SUBSURF4D_EINVAL, "check_every must be >= 0");
+    if (p->precision != SUBSURF4D_FP64 && p->precision != SUBSURF4D_MIXED)
+        return fail(SUBSURF4D_EINVAL, "unknown precision");
+    if (p->rescale && !(p->ball_r >= 0.0 && p->ball_r <= 1e6)) return fail(SUBSURF4D_EINVAL, "ball_r out of range");
+    if (p->precision == SUBSURF4D_MIXED) {
+        if (!(p->refine_tol > 0.0)) return fail(SUBSURF4D_EINVAL, "refine_tol must be > 0");
+        if (p->inner_sweeps < 1) return fail(SUBSURF4D_EINVAL, "inner_sweeps must be >= 1");
+    }
+    return 0;
+}
+
+}  // namespace
+
+#define SS4_GUARD_BEGIN try {
+#define SS4_GUARD_END                                                      \
+    }                                                                      \
+    catch (const std::exception& e) { return fail(SUBSURF4D_EDEVICE, e.what()); } \
+    catch (...) { return fail(SUBSURF4D_EDEVICE, "unknown C++ exception"); }
+
+extern "C" {
+
+size_t subsurf4d_workspace_bytes(const subsurf4d_grid* grid, int32_t n_centres, int32_t precision)
+{
+    try {
+        if (!grid || n_centres < 0) return 0;
+        for (int d = 0; d < 4; ++d)
+            if (grid->n[d] < 1 || grid->n[d] > (1 << 20)) return 0;
+        WsPlan P;
+        if (!plan_workspace(grid->n, n_centres, precision, &P)) return 0;
+        return P.total;
+    } catch (...) {
+        return 0;
+    }
+}
+
+int subsurf4d_prepare_g(const subsurf4d_grid* grid, const void* image, int32_t image_dtype,
+                        const subsurf4d_centre* centres, int32_t n_centres,
+                        const subsurf4d_prepare_params* params, double* G, int32_t* owner, void* workspace,
+                        size_t workspace_bytes, void* stream)
+{
+    SS4_GUARD_BEGIN
+    g_error.clear();
+    if (int rc = check_grid(grid)) return rc;
+    if (!image || !params || !G || !owner) return fail(SUBSURF4D_EINVAL, "NULL argument");
+    if (n_centres < 0 || (n_centres > 0 && !centres)) return fail(SUBSURF4D_EINVAL, "bad centres");
+    if (image_dtype != SUBSURF4D_U8 && image_dtype != SUBSURF4D_F32 && image_dtype != SUBSURF4D_F64)
+        return fail(SUBSURF4D_EINVAL, "unknown image dtype");
+    const subsurf4d_prepare_params& p = *params;
+    if (!(p.K >= 0.0) || !std::isfinite(p.K)) return fail(SUBSURF4D_EINVAL, "K must be >= 0");
+    if (!(p.lambda >= 0.0 && p.lambda <= 1.0)) return fail(SUBSURF4D_EINVAL, "lambda must be in [0,1]");
+    if (!(p.ball_r >= 0.0 && p.ball_r <= 1e6)) return fail(SUBSURF4D_EINVAL, "ball_r out of range");
+    if (!(p.smooth_tau >= 0.0) || p.smooth_steps < 0) return fail(SUBSURF4D_EINVAL, "bad smoothing parameters");
+    if (p.smooth_steps > 0 && (!(p.smooth_omega > 0.0 && p.smooth_omega < 2.0) || p.smooth_max_iter < 1 ||
+                               !(p.smooth_tol >= 0.0)))
+        return fail(SUBSURF4D_EINVAL, "bad smoothing solver parameters");
+    if (!std::isfinite(p.image_scale)) return fail(SUBSURF4D_EINVAL, "image_scale must be finite");
+    WsPlan P;
+    if (!plan_workspace(grid->n, n_centres, SUBSURF4D_FP64, &P)) return fail(SUBSURF4D_ESHAPE, "grid too large");
+    if (int rc = check_ws(P, workspace, workspace_bytes)) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int rc = run_prepare(P, grid->h, image, image_dtype, centres, n_centres, p, G, owner, workspace, s);
+    if (rc < 0) return rc;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "prepare");
+    return rc;
+    SS4_GUARD_END
+}
+
+int subsurf4d_init_u(const subsurf4d_grid* grid, const subsurf4d_centre* seeds, int32_t n_seeds, double v,
+                     double R, double* u, void* stream)
+{
+    SS4_GUARD_BEGIN
+    g_error.clear();
+    if (int rc = check_grid(grid)) return rc;
+    if (!u || n_seeds < 0 || (n_seeds > 0 && !seeds)) return fail(SUBSURF4D_EINVAL, "bad arguments");
+    if (!(v > 0.0) || !std::isfinite(v)) return fail(SUBSURF4D_EINVAL, "v must be positive");
+    if (!std::isfinite(R) || R > 1e6) return fail(SUBSURF4D_EINVAL, "R out of range");
+    const Layout L = make_layout(grid->n);
+    return run_init_u(L, seeds, n_seeds, v, R, u, static_cast<hipStream_t>(stream));
+    SS4_GUARD_END
+}
+
+int subsurf4d_rescale(const subsurf4d_grid* grid, const subsurf4d_centre* centres, int32_t n_centres,
+                      double ball_r, const int32_t* owner, double* u, void* workspace, size_t workspace_bytes,
+                      void* stream)
+{
+    SS4_GUARD_BEGIN
+    g_error.clear();
+    if (int rc = check_grid(grid)) return rc;
+    if (!u || !owner || n_centres < 0 || (n_centres > 0 && !centres)) return fail(SUBSURF4D_EINVAL, "bad arguments");
+    if (!(ball_r >= 0.0 && ball_r <= 1e6)) return fail(SUBSURF4D_EINVAL, "ball_r out of range");
+    WsPlan P;
+    if (!plan_workspace(grid->n, n_centres, SUBSURF4D_FP64, &P)) return fail(SUBSURF4D_ESHAPE, "grid too large");
+    if (int rc = check_ws(P, workspace, workspace_bytes)) return rc;
+    return run_rescale(P, centres, n_centres, ball_r, owner, u, workspace, static_cast<hipStream_t>(stream));
+    SS4_GUARD_END
+}
+
+int subsurf4d_assemble(const subsurf4d_grid* grid, const double* G, const double* u,
+                       const subsurf4d_step_params* params, double* coef, double* b, void* stream)
+{
+    SS4_GUARD_BEGIN
+    g_error.clear();
+    if (int rc = check_grid(grid)) return rc;
+    if (!G || !u || !coef || !b) return fail(SUBSURF4D_EINVAL, "NULL argument");
+    if (int rc = check_step_params(params)) return rc;
+    const Layout L = make_layout(grid->n);
+    return run_assemble_export(L, grid->h, G, u, *params, coef, b, static_cast<hipStream_t>(stream));
+    SS4_GUARD_END
+}
+
+int subsurf4d_step(const subsurf4d_grid* grid, const double* G, const subsurf4d_centre* centres,
+                   int32_t n_centres, const int32_t* owner, double* u, const subsurf4d_step_params* params,
+                   subsurf4d_result* result, void* workspace, size_t workspace_bytes, void* stream)
+{
+    SS4_GUARD_BEGIN
+    g_error.clear();
+    if (int rc = check_grid(grid)) return rc;
+    if (!G || !u) return fail(SUBSURF4D_EINVAL, "NULL argument");
+    if (int rc = check_step_params(params)) return rc;
+    if (params->rescale && (n_centres < 0 || (n_centres > 0 && (!centres || !owner))))
+        return fail(SUBSURF4D_EINVAL, "rescale needs centres and owner");
+    const int nc = params->rescale ? n_centres : 0;
+    WsPlan P;
+    if (!plan_workspace(grid->n, nc, params->precision, &P)) return fail(SUBSURF4D_ESHAPE, "grid too large");
+    if (int rc = check_ws(P, workspace, workspace_bytes)) return rc;
+    subsurf4d_result tmp;
+    return run_step(P, grid->h, G, centres, nc, owner, u, *params, result ? result : &tmp, workspace,
+                    static_cast<hipStream_t>(stream));
+    SS4_GUARD_END
+}
+
+int subsurf4d_solve(const subsurf4d_grid* grid, const double* coef, const double* b, double* u,
+                    const subsurf4d_step_params* params, subsurf4d_result* result, void* workspace,
+                    size_t workspace_bytes, void* stream)
+{
+    SS4_GUARD_BEGIN
+    g_error.clear();
+    if (int rc = check_grid(grid)) return rc;
+    if (!coef || !b || !u) return fail(SUBSURF4D_EINVAL, "NULL argument");
+    if (int rc = check_step_params(params)) return rc;
+    if (params->precision != SUBSURF4D_FP64) return fail(SUBSURF4D_EINVAL, "solve supports FP64 only");
+    WsPlan P;
+    if (!plan_workspace(grid->n, 0, SUBSURF4D_FP64, &P)) return fail(SUBSURF4D_ESHAPE, "grid too large");
+    if (int rc = check_ws(P, workspace, workspace_bytes)) return rc;
+    subsurf4d_result tmp;
+    return run_solve(P, coef, b, u, *params, result ? result : &tmp, workspace, static_cast<hipStream_t>(stream));
+    SS4_GUARD_END
+}
+
+const char* subsurf4d_status_string(int status)
+{
+    switch (status) {
+    case SUBSURF4D_OK: return "ok";
+    case SUBSURF4D_NOT_CONVERGED: return "not converged (iteration cap reached)";
+    case SUBSURF4D_EINVAL: return "invalid argument";
+    case SUBSURF4D_ESHAPE: return "unsupported grid shape";
+    case SUBSURF4D_EWORKSPACE: return "workspace too small";
+    case SUBSURF4D_ENONFINITE: return "non-finite value";
+    case SUBSURF4D_EDEVICE: return "HIP device error";
+    default: return "unknown status";
+    }
+}
+
+const char* subsurf4d_last_error(void) { return g_error.c_str(); }
+
+const char* subsurf4d_version(void) { return "subsurf4d 0.1 (gfx950)"; }
+
+void subsurf4d_timing(int32_t op, double* sweep_ms, int64_t* sweep_launches, int64_t* voxel_updates,
+                      int64_t* solves)
+{
+    std::lock_guard<std::mutex> g(g_timing_mu);
+    if (op == 1 || op == 0) g_timing_on = (op == 1);
+    if (op == 2) g_timing = TimingTotals();
+    if (sweep_ms) *sweep_ms = g_timing.sweep_ms;
+    if (sweep_launches) *sweep_launches = g_timing.sweep_launches;
+    if (voxel_updates) *voxel_updates = g_timing.voxel_updates;
+    if (solves) *solves = g_timing.solves;
+}
+
+}  // extern "C"

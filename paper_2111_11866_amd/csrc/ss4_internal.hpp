@@ -1,0 +1,125 @@
+// Internal host-side interface between the C ABI and the kernel launchers.
+#pragma once
+
+#include <string>
+
+#include "ss4_common.hpp"
+
+namespace ss4 {
+
+// Carving of the caller's workspace.  A small region (control block, per-block
+// partials, per-ball scalars) is followed by a large region that the
+// preparation and the time step use at different times.
+struct WsPlan {
+    Layout L;
+    int32_t n_centres = 0;
+    int32_t precision = 0;
+    size_t ctrl = 0, part_a = 0, part_b = 0, balls = 0, big = 0;
+    // time step
+    size_t ured0 = 0, ured1 = 0, ublack = 0, coef = 0, rhs = 0;
+    // mixed precision (inside the step region)
+    size_t xf64 = 0, rf32 = 0, dred0 = 0, dred1 = 0, dblack = 0, coef16 = 0, rhs32 = 0;
+    // preparation
+    size_t I0 = 0, ITH = 0, S0 = 0, S1 = 0;
+    size_t step_bytes = 0, prep_bytes = 0, total = 0;
+};
+
+bool plan_workspace(const int32_t n[4], int32_t n_centres, int32_t precision, WsPlan* P);
+
+template <typename T>
+inline T* ws_ptr(void* ws, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + off); }
+
+// Every launcher returns 0 or a negative SUBSURF4D_* status and sets the
+// thread-local error text on failure.
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define SS4_HIP(call)                                       \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return ss4::hip_fail(e_, #call); \
+    } while (0)
+
+#define SS4_LAUNCHED(what)                                  \
+    do {                                                    \
+        hipError_t e_ = hipGetLastError();                  \
+        if (e_ != hipSuccess) return ss4::hip_fail(e_, what); \
+    } while (0)
+
+// preparation (prepare.hip)
+int run_prepare(const WsPlan& P, double h, const void* image, int dtype,
+                const subsurf4d_centre* centres, int nc, const subsurf4d_prepare_params& pp,
+                double* G, int32_t* owner, void* ws, hipStream_t s);
+int run_init_u(const Layout& L, const subsurf4d_centre* seeds, int ns, double v, double R,
+               double* u, hipStream_t s);
+int run_rescale(const WsPlan& P, const subsurf4d_centre* centres, int nc, double r,
+                const int32_t* owner, double* u, void* ws, hipStream_t s);
+
+// time step and solve (solve.hip)
+int run_assemble_export(const Layout& L, double h, const double* G, const double* u,
+                        const subsurf4d_step_params& sp, double* coef, double* b, hipStream_t s);
+int run_step(const WsPlan& P, double h, const double* G, const subsurf4d_centre* centres, int nc,
+             const int32_t* owner, double* u, const subsurf4d_step_params& sp,
+             subsurf4d_result* res, void* ws, hipStream_t s);
+int run_solve(const WsPlan& P, const double* coef, const double* b, double* u,
+              const subsurf4d_step_params& sp, subsurf4d_result* res, void* ws, hipStream_t s);
+
+// the red-black iteration on a loaded system (solve.hip); used by step/solve
+int run_sor_loop(const WsPlan& P, const subsurf4d_step_params& sp, void* ws, hipStream_t s,
+                 subsurf4d_result* res);
+int run_unsplit(const WsPlan& P, double* u, void* ws, hipStream_t s);
+
+// mixed precision (mixed.hip)
+int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
+                    const subsurf4d_step_params& sp, subsurf4d_result* res, void* ws,
+                    hipStream_t s);
+
+}  // namespace ss4
+
+namespace ss4 {
+
+// Optional HIP-event timing of the red-black sweep chunks (enabled through
+// subsurf4d_timing).  Events are recorded on the stream the sweeps run on.
+struct TimingTotals {
+    double sweep_ms = 0.0;        // summed duration of sweep chunks
+    int64_t sweep_launches = 0;   // sweep launches that did work
+    int64_t voxel_updates = 0;    // iterations x interior cells
+    int64_t solves = 0;
+};
+bool timing_enabled();
+void timing_add(double ms, int64_t launches, int64_t updates);
+
+class SweepTimer {
+public:
+    explicit SweepTimer(hipStream_t s) : s_(s), on_(timing_enabled())
+    {
+        if (on_) {
+            on_ = hipEventCreate(&a_) == hipSuccess && hipEventCreate(&b_) == hipSuccess;
+        }
+    }
+    ~SweepTimer()
+    {
+        if (a_) (void)hipEventDestroy(a_);
+        if (b_) (void)hipEventDestroy(b_);
+    }
+    void begin() { if (on_) (void)hipEventRecord(a_, s_); }
+    void end() { if (on_) (void)hipEventRecord(b_, s_); }
+    void collect()
+    {
+        if (!on_) return;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, a_, b_) == hipSuccess) ms_ += ms;
+    }
+    void account(int64_t launches, int64_t updates)
+    {
+        if (on_) timing_add(ms_, launches, updates);
+    }
+
+private:
+    hipStream_t s_;
+    bool on_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+    double ms_ = 0.0;
+};
+
+}  // namespace ss4

@@ -1,0 +1,506 @@
+// Per-job preparation kernels: ball ownership, local thresholding,
+// implicit zero-Neumann presmoothing, face edge detector G, initial function,
+// local rescaling (Sec. 3.1 and Sec. 3.2.2 of the paper).
+#include <climits>
+#include <cmath>
+
+#include "ss4_internal.hpp"
+
+namespace ss4 {
+namespace {
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Bounding box of B(c, r) in 1-based interior indices with one voxel of slack;
+// membership is decided by the exact squared distance.
+struct Box {
+    int lo[3], hi[3], w[3];
+    int64_t count;
+};
+
+__device__ __forceinline__ Box ball_box(const Layout& L, const subsurf4d_centre& c, double r)
+{
+    Box b;
+    const double cc[3] = {(double)c.x, (double)c.y, (double)c.z};
+    const int n[3] = {L.n1, L.n2, L.n3};
+    b.count = 1;
+    for (int a = 0; a < 3; ++a) {
+        b.lo[a] = clampi((int)floor(cc[a] - r), 1, n[a]);
+        b.hi[a] = clampi((int)ceil(cc[a] + r) + 2, 1, n[a]);
+        b.w[a] = b.hi[a] - b.lo[a] + 1;
+        b.count *= b.w[a];
+    }
+    return b;
+}
+
+__device__ __forceinline__ void box_cell(const Box& b, int64_t q, int& i, int& j, int& k)
+{
+    i = b.lo[0] + (int)(q % b.w[0]);
+    const int64_t q2 = q / b.w[0];
+    j = b.lo[1] + (int)(q2 % b.w[1]);
+    k = b.lo[2] + (int)(q2 / b.w[1]);
+}
+
+__device__ __forceinline__ double cell_dist2(const subsurf4d_centre& c, int i, int j, int k)
+{
+    return dist2_exact((double)(i - 1) - (double)c.x, (double)(j - 1) - (double)c.y,
+                       (double)(k - 1) - (double)c.z);
+}
+
+__device__ __forceinline__ int64_t iidx(const Layout& L, int i, int j, int k, int l)
+{
+    return (((int64_t)(l - 1) * L.n3 + (k - 1)) * L.n2 + (j - 1)) * L.n1 + (i - 1);
+}
+
+__device__ __forceinline__ int64_t pidx(const Layout& L, int i, int j, int k, int l)
+{
+    return (((int64_t)l * L.p3 + k) * L.p2 + j) * L.p1 + i;
+}
+
+__device__ __forceinline__ bool frame_ok(const Layout& L, const subsurf4d_centre& c)
+{
+    return c.frame >= 0 && c.frame < L.n4;
+}
+
+// ------------------------------------------------------------ fills / casts
+
+__global__ void k_fill_u64(uint64_t* a, int64_t n, uint64_t v)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        a[q] = v;
+}
+
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        a[q] = v;
+}
+
+__global__ void k_fill_f64(double* a, int64_t n, double v)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        a[q] = v;
+}
+
+__global__ void k_copy_f64(const double* __restrict__ a, double* __restrict__ b, int64_t n)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        b[q] = a[q];
+}
+
+__global__ void k_image_to_f64(const void* img, int dtype, double scale, double* out, int64_t n)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        double v;
+        if (dtype == SUBSURF4D_U8) v = (double)static_cast<const uint8_t*>(img)[q];
+        else if (dtype == SUBSURF4D_F32) v = (double)static_cast<const float*>(img)[q];
+        else v = static_cast<const double*>(img)[q];
+        out[q] = __dmul_rn(scale, v);
+    }
+}
+
+// ------------------------------------------------------------ ownership
+
+// Pass 1: smallest squared distance to a containing centre, per cell.
+__global__ void k_owner_pass1(Layout L, const subsurf4d_centre* cs, double r, uint64_t* key)
+{
+    const subsurf4d_centre c = cs[blockIdx.x];
+    if (!frame_ok(L, c)) return;
+    const Box b = ball_box(L, c, r);
+    const double r2 = __dmul_rn(r, r);
+    for (int64_t q = threadIdx.x; q < b.count; q += blockDim.x) {
+        int i, j, k;
+        box_cell(b, q, i, j, k);
+        const double d2 = cell_dist2(c, i, j, k);
+        if (d2 <= r2)
+            atomicMin((unsigned long long*)&key[iidx(L, i, j, k, c.frame + 1)],
+                      (unsigned long long)__double_as_longlong(d2));
+    }
+}
+
+// Pass 2: among the centres at that distance, the lowest index owns the cell.
+__global__ void k_owner_pass2(Layout L, const subsurf4d_centre* cs, double r, const uint64_t* key,
+                              int32_t* owner)
+{
+    const int m = blockIdx.x;
+    const subsurf4d_centre c = cs[m];
+    if (!frame_ok(L, c)) return;
+    const Box b = ball_box(L, c, r);
+    const double r2 = __dmul_rn(r, r);
+    for (int64_t q = threadIdx.x; q < b.count; q += blockDim.x) {
+        int i, j, k;
+        box_cell(b, q, i, j, k);
+        const double d2 = cell_dist2(c, i, j, k);
+        if (d2 <= r2) {
+            const int64_t cell = iidx(L, i, j, k, c.frame + 1);
+            if (key[cell] == (uint64_t)__double_as_longlong(d2)) atomicMin(&owner[cell], m);
+        }
+    }
+}
+
+__global__ void k_owner_fix(int32_t* owner, int64_t n)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        if (owner[q] == INT_MAX) owner[q] = -1;
+}
+
+// min / max of a field over each ball (one block per ball).
+__global__ void k_ball_minmax(Layout L, const subsurf4d_centre* cs, double r, const double* f,
+                              int padded, double* mn, double* mx)
+{
+    __shared__ double s_lo[4], s_hi[4];
+    const int m = blockIdx.x;
+    const subsurf4d_centre c = cs[m];
+    double lo = INFINITY, hi = -INFINITY;
+    if (frame_ok(L, c)) {
+        const Box b = ball_box(L, c, r);
+        const double r2 = __dmul_rn(r, r);
+        for (int64_t q = threadIdx.x; q < b.count; q += blockDim.x) {
+            int i, j, k;
+            box_cell(b, q, i, j, k);
+            if (cell_dist2(c, i, j, k) <= r2) {
+                const double v = padded ? f[pidx(L, i, j, k, c.frame + 1)] : f[iidx(L, i, j, k, c.frame + 1)];
+                lo = fmin(lo, v);
+                hi = fmax(hi, v);
+            }
+        }
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if ((threadIdx.x & 63) == 0) { s_lo[threadIdx.x >> 6] = lo; s_hi[threadIdx.x >> 6] = hi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        mn[m] = fmin(fmin(s_lo[0], s_lo[1]), fmin(s_lo[2], s_lo[3]));
+        mx[m] = fmax(fmax(s_hi[0], s_hi[1]), fmax(s_hi[2], s_hi[3]));
+    }
+}
+
+// Local thresholding (Sec. 3.1): beta where I0 >= TH, alpha otherwise, on owned cells.
+__global__ void k_threshold(int64_t n, const double* I0, const int32_t* owner, const double* alpha,
+                            const double* beta, double lam, double* ITH)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int m = owner[q];
+        if (m < 0) { ITH[q] = I0[q]; continue; }
+        const double a = alpha[m], b = beta[m];
+        const double th = threshold_exact(lam, a, b);
+        ITH[q] = (I0[q] >= th) ? b : a;
+    }
+}
+
+// Local rescaling map on owned cells (one block per ball; each cell has one owner).
+__global__ void k_ball_map(Layout L, const subsurf4d_centre* cs, double r, const int32_t* owner,
+                           const double* mu, const double* xi, double* u)
+{
+    const int m = blockIdx.x;
+    const subsurf4d_centre c = cs[m];
+    if (!frame_ok(L, c)) return;
+    const double lo = mu[m], span = __dsub_rn(xi[m], lo);
+    if (!(span >= 1e-12)) return;
+    const Box b = ball_box(L, c, r);
+    const double r2 = __dmul_rn(r, r);
+    for (int64_t q = threadIdx.x; q < b.count; q += blockDim.x) {
+        int i, j, k;
+        box_cell(b, q, i, j, k);
+        if (cell_dist2(c, i, j, k) <= r2 && owner[iidx(L, i, j, k, c.frame + 1)] == m) {
+            const int64_t p = pidx(L, i, j, k, c.frame + 1);
+            u[p] = __ddiv_rn(__dsub_rn(u[p], lo), span);
+        }
+    }
+}
+
+// ---------------------------------------------------- implicit heat step
+//
+// (1 + a n_P) J_P - a sum_{interior nbrs} J_nbr = rhs_P, a = tau_s/h^2, zero
+// Neumann boundary (no flux through boundary faces), red-black SOR.
+
+template <int COLOR>
+__global__ __launch_bounds__(kBlock) void k_lhe_sweep(Layout L, double a, double omega,
+                                                      const double* __restrict__ rhs, double* J,
+                                                      const Ctrl* C)
+{
+    if (C->done) return;
+    const int64_t sy = L.n1, sz = (int64_t)L.n1 * L.n2, st = sz * L.n3;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < L.nint; q += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(q % L.n1) + 1;
+        const int64_t row = q / L.n1;
+        const int j = (int)(row % L.n2) + 1;
+        const int64_t r2 = row / L.n2;
+        const int k = (int)(r2 % L.n3) + 1;
+        const int l = (int)(r2 / L.n3) + 1;
+        if (((i + j + k + l) & 1) != COLOR) continue;
+        double s = rhs[q];
+        int cnt = 0;
+        if (i > 1) { s += a * J[q - 1]; ++cnt; }
+        if (i < L.n1) { s += a * J[q + 1]; ++cnt; }
+        if (j > 1) { s += a * J[q - sy]; ++cnt; }
+        if (j < L.n2) { s += a * J[q + sy]; ++cnt; }
+        if (k > 1) { s += a * J[q - sz]; ++cnt; }
+        if (k < L.n3) { s += a * J[q + sz]; ++cnt; }
+        if (l > 1) { s += a * J[q - st]; ++cnt; }
+        if (l < L.n4) { s += a * J[q + st]; ++cnt; }
+        const double D = 1.0 + a * cnt;
+        J[q] = omega * (s / D) + (1.0 - omega) * J[q];
+    }
+}
+
+// Residual ||rhs - A J||_2 (and ||rhs||_2 at k = 0); the last block applies the
+// stopping rule of the heat solve.
+__global__ __launch_bounds__(kBlock) void k_lhe_residual(Layout L, double a, const double* __restrict__ rhs,
+                                                         const double* __restrict__ J, int k, double* part_r,
+                                                         double* part_b, Ctrl* C)
+{
+    __shared__ double lds[4];
+    __shared__ int flag;
+    if (C->done) return;
+    const int64_t sy = L.n1, sz = (int64_t)L.n1 * L.n2, st = sz * L.n3;
+    double ar = 0.0, ab = 0.0;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < L.nint; q += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(q % L.n1) + 1;
+        const int64_t row = q / L.n1;
+        const int j = (int)(row % L.n2) + 1;
+        const int64_t r2 = row / L.n2;
+        const int kk = (int)(r2 % L.n3) + 1;
+        const int l = (int)(r2 / L.n3) + 1;
+        double s = rhs[q];
+        int cnt = 0;
+        if (i > 1) { s += a * J[q - 1]; ++cnt; }
+        if (i < L.n1) { s += a * J[q + 1]; ++cnt; }
+        if (j > 1) { s += a * J[q - sy]; ++cnt; }
+        if (j < L.n2) { s += a * J[q + sy]; ++cnt; }
+        if (kk > 1) { s += a * J[q - sz]; ++cnt; }
+        if (kk < L.n3) { s += a * J[q + sz]; ++cnt; }
+        if (l > 1) { s += a * J[q - st]; ++cnt; }
+        if (l < L.n4) { s += a * J[q + st]; ++cnt; }
+        const double r = s - (1.0 + a * cnt) * J[q];
+        ar += r * r;
+        if (k == 0) ab += rhs[q] * rhs[q];
+    }
+    const double br = block_sum(ar, lds);
+    const double bb = block_sum(ab, lds);
+    if (threadIdx.x == 0) { part_r[blockIdx.x] = br; part_b[blockIdx.x] = bb; }
+    if (!arrive_last(&C->arrive[3], gridDim.x, &flag)) return;
+    const double R2 = sum_partials(part_r, gridDim.x, lds);
+    const double B2 = k == 0 ? sum_partials(part_b, gridDim.x, lds) : 0.0;
+    if (threadIdx.x == 0) {
+        if (k == 0) C->bn = sqrt(B2);
+        const double R = sqrt(R2);
+        C->rel_res = C->bn > 0.0 ? R / C->bn : R;
+        C->iterations = k;
+        if (!(R2 < INFINITY)) { C->status = SUBSURF4D_ENONFINITE; C->done = 1; }
+        else if (R <= C->tol * C->bn) C->done = 1;
+        else if (k >= C->max_iter) { C->status = SUBSURF4D_NOT_CONVERGED; C->done = 1; }
+        C->arrive[3] = 0;
+    }
+}
+
+// --------------------------------------------------------- edge detector G
+
+// interior array read with clamped indices (image outside the box = nearest value)
+__device__ __forceinline__ double clamped(const Layout& L, const double* v, int i, int j, int k, int l)
+{
+    return v[iidx(L, clampi(i, 1, L.n1), clampi(j, 1, L.n2), clampi(k, 1, L.n3), clampi(l, 1, L.n4))];
+}
+
+// |reduced-diamond-cell gradient|^2 on the +e_d face of cell (i,j,k,l)
+__device__ double face_q_clamped(const Layout& L, const double* v, int i, int j, int k, int l, int d,
+                                 double inv_h)
+{
+    int P[4] = {i, j, k, l};
+    int Q[4] = {i, j, k, l};
+    Q[d] += 1;
+    const double vP = clamped(L, v, P[0], P[1], P[2], P[3]);
+    const double vQ = clamped(L, v, Q[0], Q[1], Q[2], Q[3]);
+    double g = (vQ - vP) * inv_h;
+    double q = g * g;
+    for (int t = 0; t < 4; ++t) {
+        if (t == d) continue;
+        int Pp[4] = {P[0], P[1], P[2], P[3]}, Pm[4] = {P[0], P[1], P[2], P[3]};
+        int Qp[4] = {Q[0], Q[1], Q[2], Q[3]}, Qm[4] = {Q[0], Q[1], Q[2], Q[3]};
+        Pp[t] += 1; Pm[t] -= 1; Qp[t] += 1; Qm[t] -= 1;
+        const double tg = ((clamped(L, v, Pp[0], Pp[1], Pp[2], Pp[3]) + clamped(L, v, Qp[0], Qp[1], Qp[2], Qp[3])) -
+                           (clamped(L, v, Pm[0], Pm[1], Pm[2], Pm[3]) + clamped(L, v, Qm[0], Qm[1], Qm[2], Qm[3]))) *
+                          (0.25 * inv_h);
+        q += tg * tg;
+    }
+    return q;
+}
+
+__global__ __launch_bounds__(kBlock) void k_face_g(Layout L, double inv_h, double K, double delta,
+                                                   double vartheta, const double* S0, const double* S1,
+                                                   double* G)
+{
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < L.npad; p += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(p % L.p1);
+        const int64_t row = p / L.p1;
+        const int j = (int)(row % L.p2);
+        const int64_t r2 = row / L.p2;
+        const int k = (int)(r2 % L.p3);
+        const int l = (int)(r2 / L.p3);
+        for (int d = 0; d < 4; ++d) {
+            const double n0 = sqrt(face_q_clamped(L, S0, i, j, k, l, d, inv_h));
+            const double n1 = sqrt(face_q_clamped(L, S1, i, j, k, l, d, inv_h));
+            const double s = delta * n0 + vartheta * n1;
+            G[(int64_t)d * L.npad + p] = 1.0 / (1.0 + K * (s * s));
+        }
+    }
+}
+
+// ------------------------------------------------------- initial function
+
+// R <= 0: every interior cell takes the max over its frame's seeds of 1/(|X-s|+v).
+__global__ void k_init_u_dense(Layout L, const subsurf4d_centre* seeds, int ns, double v, double* u)
+{
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < L.npad; p += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(p % L.p1);
+        const int64_t row = p / L.p1;
+        const int j = (int)(row % L.p2);
+        const int64_t r2 = row / L.p2;
+        const int k = (int)(r2 % L.p3);
+        const int l = (int)(r2 / L.p3);
+        double best = 0.0;
+        if (i >= 1 && i <= L.n1 && j >= 1 && j <= L.n2 && k >= 1 && k <= L.n3 && l >= 1 && l <= L.n4) {
+            bool any = false;
+            for (int m = 0; m < ns; ++m) {
+                const subsurf4d_centre c = seeds[m];
+                if (c.frame != l - 1) continue;
+                const double val = __ddiv_rn(1.0, __dadd_rn(__dsqrt_rn(cell_dist2(c, i, j, k)), v));
+                if (!any || val > best) best = val;
+                any = true;
+            }
+        }
+        u[p] = best;
+    }
+}
+
+// R > 0: scatter max(0, 1/(|X-s|+v) - 1/(R+v)) over the seed's R-box (u starts at 0;
+// non-negative doubles order like their bit patterns, so an integer max is exact).
+__global__ void k_init_u_scatter(Layout L, const subsurf4d_centre* seeds, double v, double R, double* u)
+{
+    const subsurf4d_centre c = seeds[blockIdx.x];
+    if (!frame_ok(L, c)) return;
+    const Box b = ball_box(L, c, R);
+    const double shift = __ddiv_rn(1.0, __dadd_rn(R, v));
+    for (int64_t q = threadIdx.x; q < b.count; q += blockDim.x) {
+        int i, j, k;
+        box_cell(b, q, i, j, k);
+        const double val = __dsub_rn(__ddiv_rn(1.0, __dadd_rn(__dsqrt_rn(cell_dist2(c, i, j, k)), v)), shift);
+        if (val > 0.0)
+            atomicMax((unsigned long long*)&u[pidx(L, i, j, k, c.frame + 1)],
+                      (unsigned long long)__double_as_longlong(val));
+    }
+}
+
+int lhe_solve(const WsPlan& P, double a, double omega, double tol, int max_iter, const double* rhs,
+              double* J, void* ws, hipStream_t s, int* status)
+{
+    const Layout& L = P.L;
+    Ctrl* C = ws_ptr<Ctrl>(ws, P.ctrl);
+    double* pa = ws_ptr<double>(ws, P.part_a);
+    double* pb = ws_ptr<double>(ws, P.part_b);
+    const int gs = grid_for(L.nint);
+    const int gr = grid_for(L.nint);
+    k_copy_f64<<<grid_for(L.nint), kBlock, 0, s>>>(rhs, J, L.nint);
+    k_ctrl_init<<<1, 64, 0, s>>>(C, tol, max_iter);
+    k_lhe_residual<<<gr, kBlock, 0, s>>>(L, a, rhs, J, 0, pa, pb, C);
+    SS4_LAUNCHED("lhe residual");
+    Ctrl hc;
+    int k = 1, chunk = 4;
+    for (;;) {
+        SS4_HIP(hipMemcpyAsync(&hc, C, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+        SS4_HIP(hipStreamSynchronize(s));
+        if (hc.done) break;
+        if (k > max_iter) {
+            set_error("internal: heat solve ended without a decision");
+            return SUBSURF4D_EDEVICE;
+        }
+        for (int c = 0; c < chunk && k <= max_iter; ++c, ++k) {
+            k_lhe_sweep<0><<<gs, kBlock, 0, s>>>(L, a, omega, rhs, J, C);
+            k_lhe_sweep<1><<<gs, kBlock, 0, s>>>(L, a, omega, rhs, J, C);
+            k_lhe_residual<<<gr, kBlock, 0, s>>>(L, a, rhs, J, k, pa, pb, C);
+        }
+        SS4_LAUNCHED("lhe sweeps");
+        if (chunk < 32) chunk *= 2;
+    }
+    if (hc.status == SUBSURF4D_ENONFINITE) {
+        set_error("non-finite residual in the presmoothing solve");
+        return SUBSURF4D_ENONFINITE;
+    }
+    if (hc.status == SUBSURF4D_NOT_CONVERGED) *status = SUBSURF4D_NOT_CONVERGED;
+    return 0;
+}
+
+}  // namespace
+
+int run_prepare(const WsPlan& P, double h, const void* image, int dtype, const subsurf4d_centre* centres,
+                int nc, const subsurf4d_prepare_params& pp, double* G, int32_t* owner, void* ws,
+                hipStream_t s)
+{
+    const Layout& L = P.L;
+    double* I0 = ws_ptr<double>(ws, P.I0);
+    double* ITH = ws_ptr<double>(ws, P.ITH);
+    double* S0 = ws_ptr<double>(ws, P.S0);
+    double* S1 = ws_ptr<double>(ws, P.S1);
+    uint64_t* key = ws_ptr<uint64_t>(ws, P.S0);  // dead before the smoothing starts
+    double* alpha = ws_ptr<double>(ws, P.balls);
+    double* beta = alpha + (nc > 0 ? nc : 1);
+    const int gi = grid_for(L.nint);
+
+    k_image_to_f64<<<gi, kBlock, 0, s>>>(image, dtype, pp.image_scale, I0, L.nint);
+    k_fill_i32<<<gi, kBlock, 0, s>>>(owner, L.nint, INT_MAX);
+    if (nc > 0) {
+        k_fill_u64<<<gi, kBlock, 0, s>>>(key, L.nint, ~0ull);
+        k_owner_pass1<<<nc, kBlock, 0, s>>>(L, centres, pp.ball_r, key);
+        k_owner_pass2<<<nc, kBlock, 0, s>>>(L, centres, pp.ball_r, key, owner);
+        k_ball_minmax<<<nc, kBlock, 0, s>>>(L, centres, pp.ball_r, I0, 0, alpha, beta);
+    }
+    k_owner_fix<<<gi, kBlock, 0, s>>>(owner, L.nint);
+    k_threshold<<<gi, kBlock, 0, s>>>(L.nint, I0, owner, alpha, beta, pp.lambda, ITH);
+    SS4_LAUNCHED("prepare: ownership / threshold");
+
+    // presmoothing: ping-pong between the source buffer and S0 / S1
+    int status = 0;
+    double* src0 = I0;
+    double* dst0 = S0;
+    double* src1 = ITH;
+    double* dst1 = S1;
+    const double a = pp.smooth_tau / (h * h);
+    for (int step = 0; step < pp.smooth_steps; ++step) {
+        int rc = lhe_solve(P, a, pp.smooth_omega, pp.smooth_tol, pp.smooth_max_iter, src0, dst0, ws, s, &status);
+        if (rc) return rc;
+        rc = lhe_solve(P, a, pp.smooth_omega, pp.smooth_tol, pp.smooth_max_iter, src1, dst1, ws, s, &status);
+        if (rc) return rc;
+        double* t0 = src0; src0 = dst0; dst0 = t0;
+        double* t1 = src1; src1 = dst1; dst1 = t1;
+    }
+    k_face_g<<<grid_for(L.npad), kBlock, 0, s>>>(L, 1.0 / h, pp.K, pp.delta, pp.vartheta, src0, src1, G);
+    SS4_LAUNCHED("prepare: face G");
+    return status;
+}
+
+int run_init_u(const Layout& L, const subsurf4d_centre* seeds, int ns, double v, double R, double* u,
+               hipStream_t s)
+{
+    if (R > 0.0) {
+        k_fill_f64<<<grid_for(L.npad), kBlock, 0, s>>>(u, L.npad, 0.0);
+        if (ns > 0) k_init_u_scatter<<<ns, kBlock, 0, s>>>(L, seeds, v, R, u);
+    } else {
+        k_init_u_dense<<<grid_for(L.npad), kBlock, 0, s>>>(L, seeds, ns, v, u);
+    }
+    SS4_LAUNCHED("init_u");
+    return 0;
+}
+
+int run_rescale(const WsPlan& P, const subsurf4d_centre* centres, int nc, double r, const int32_t* owner,
+                double* u, void* ws, hipStream_t s)
+{
+    if (nc <= 0) return 0;
+    double* mu = ws_ptr<double>(ws, P.balls);
+    double* xi = mu + nc;
+    k_ball_minmax<<<nc, kBlock, 0, s>>>(P.L, centres, r, u, 1, mu, xi);
+    k_ball_map<<<nc, kBlock, 0, s>>>(P.L, centres, r, owner, mu, xi, u);
+    SS4_LAUNCHED("rescale");
+    return 0;
+}
+
+}  // namespace ss4
