@@ -38,6 +38,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("paper_2111_11866_amd/csrc/ss4_solve.hip", "paper_2111_11866_amd/csrc/ss4_common.hpp")
+COUNTER_SUMMARY = "profiles/k_sweep_config2_counters.md"
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic():
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a
+    copy of known size), or None when the kernel sources changed since."""
+    path = os.path.join(ROOT, COUNTER_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    if "```json" not in txt:
+        return None
+    d = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+    if d.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return d
+
+
 def cpu_baseline(img, pp, sp, seconds):
     """The oracle's red-black SOR (all host threads) on a bounded crop of the
     same image: 128 x 128 x 96 voxels x 4 frames, one step's system."""
@@ -158,11 +188,24 @@ def main():
         "hbm_frac_sweeps": achieved / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sweep (red and black half-sweeps)",
+                     "kernel": "red-black half-sweep (k_sweep_tm, red and black)",
                      "avg_launch_ms": launch_ms, "launches": tm["sweep_launches"],
                      "bytes_per_launch": bytes_per_launch},
         "sweep_share_of_step_time": tm["sweep_ms"] / (dt * 1e3),
     }
+    ct = counter_traffic()
+    if ct is not None:
+        out["roofline"]["traffic"] = ct["hbm_bytes_per_launch"]
+        out["roofline"]["traffic_source"] = COUNTER_SUMMARY
+    # practical HBM bandwidth of a plain 16-byte copy (4 GiB read + 4 GiB written)
+    nb = 1 << 32
+    src = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    ms = B.copy_probe(src, dst, reps=5)
+    out["copy_probe"] = {"bytes_moved": 2 * nb, "ms": ms, "GBs": 2 * nb / (ms * 1e-3) / 1e9,
+                         "frac_of_peak": 2 * nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    del src, dst
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(img, pp, sp, args.cpu_seconds)

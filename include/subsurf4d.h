@@ -212,6 +212,17 @@ int subsurf4d_solve(const subsurf4d_grid* grid, const double* coef, const double
                     const subsurf4d_step_params* params, subsurf4d_result* result,
                     void* workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * Bandwidth probe and counter calibration: copies `bytes` (a multiple of 16)
+ * from src to dst (device, 16-byte aligned, not overlapping) with a plain
+ * 16-byte-per-lane copy kernel, once untimed and then `reps` times between two
+ * HIP events on `stream`; *ms (host) receives the mean time of one copy.
+ * Synchronises `stream`.  Not part of the method; used to state the
+ * practical HBM bandwidth next to the roofline and to scale the hardware
+ * byte counters (a copy of known size).
+ */
+int subsurf4d_copy_probe(const void* src, void* dst, size_t bytes, int32_t reps, double* ms, void* stream);
+
 /* Static text for a status code. */
 const char* subsurf4d_status_string(int status);
 

@@ -26,7 +26,7 @@ CENTRE_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("z", "<f4"), ("frame", "<i
 EXPORTED = (
     "subsurf4d_workspace_bytes", "subsurf4d_prepare_g", "subsurf4d_init_u", "subsurf4d_rescale",
     "subsurf4d_assemble", "subsurf4d_step", "subsurf4d_solve", "subsurf4d_status_string",
-    "subsurf4d_last_error", "subsurf4d_version", "subsurf4d_timing",
+    "subsurf4d_last_error", "subsurf4d_version", "subsurf4d_timing", "subsurf4d_copy_probe",
 )
 
 
@@ -136,6 +136,7 @@ def lib():
         L.subsurf4d_version.restype = ctypes.c_char_p
         L.subsurf4d_timing.argtypes = [I, P, P, P, P]
         L.subsurf4d_timing.restype = None
+        L.subsurf4d_copy_probe.argtypes = [P, P, SZ, I, P, P]
         _lib = L
     return _lib
 
@@ -244,6 +245,15 @@ def timing(op: int = 3) -> dict:
     la, up, so = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
     lib().subsurf4d_timing(int(op), ctypes.byref(ms), ctypes.byref(la), ctypes.byref(up), ctypes.byref(so))
     return dict(sweep_ms=ms.value, sweep_launches=la.value, voxel_updates=up.value, solves=so.value)
+
+
+def copy_probe(src, dst, reps=10, stream=None) -> float:
+    """Mean ms of one 16-byte-access copy of src into dst (same byte size)."""
+    ms = ctypes.c_double(0.0)
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() >= nbytes
+    _check(lib().subsurf4d_copy_probe(_p(src), _p(dst), nbytes, int(reps), ctypes.byref(ms), _stream(stream)))
+    return ms.value
 
 
 def version() -> str:

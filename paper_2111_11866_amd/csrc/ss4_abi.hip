@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <map>
 #include <mutex>
 #include <string>
 
@@ -36,6 +37,27 @@ void timing_add(double ms, int64_t launches, int64_t updates)
     g_timing.solves += 1;
 }
 
+int resident_grid(const void* kernel)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, int> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> g(mu);
+    auto key = std::make_pair(dev, kernel);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess || per <= 0) per = 1;
+    int64_t grid = (int64_t)per * cus;
+    grid = grid / kXcd * kXcd;
+    if (grid < kXcd) grid = kXcd;
+    if (grid > kGridCap) grid = kGridCap;
+    cache[key] = (int)grid;
+    return (int)grid;
+}
+
 int hip_fail(hipError_t e, const char* what)
 {
     g_error = std::string(what) + ": " + hipGetErrorString(e);
@@ -53,8 +75,10 @@ bool plan_workspace(const int32_t n[4], int32_t n_centres, int32_t precision, Ws
     P->precision = precision;
     size_t off = 0;
     P->ctrl = off; off += align256(sizeof(Ctrl));
-    P->part_a = off; off += align256(sizeof(double) * kGridCap);
-    P->part_b = off; off += align256(sizeof(double) * kGridCap);
+    const int64_t ncol = (int64_t)L.ntm * ((L.n2 + 3) >> 2) * L.n3;   // one-block-per-column sweeps
+    P->max_grid = ncol + kXcd > kGridCap ? ncol + kXcd : kGridCap;
+    P->part_a = off; off += align256(sizeof(double) * P->max_grid);
+    P->part_b = off; off += align256(sizeof(double) * P->max_grid);
     P->balls = off; off += align256(sizeof(double) * 2 * (size_t)(n_centres > 0 ? n_centres : 1));
     P->big = off;
 
@@ -62,8 +86,7 @@ bool plan_workspace(const int32_t n[4], int32_t n_centres, int32_t precision, Ws
     P->ured0 = s; s += align256(sizeof(double) * L.usplit);
     P->ured1 = s; s += align256(sizeof(double) * L.usplit);
     P->ublack = s; s += align256(sizeof(double) * L.usplit);
-    P->coef = s; s += align256(sizeof(double) * 16 * L.csplit);
-    P->rhs = s; s += align256(sizeof(double) * 2 * L.csplit);
+    P->coef = s; s += align256(sizeof(double) * 2 * L.cblk);     // coefficients + rhs, tiled
     if (precision == SUBSURF4D_MIXED) {
         P->xf64 = s; s += align256(sizeof(double) * L.npad);          // FP64 iterate (padded)
         P->rf32 = s; s += align256(sizeof(float) * 2 * L.csplit);     // FP32 residual, split
@@ -276,6 +299,18 @@ int subsurf4d_solve(const subsurf4d_grid* grid, const double* coef, const double
     if (int rc = check_ws(P, workspace, workspace_bytes)) return rc;
     subsurf4d_result tmp;
     return run_solve(P, coef, b, u, *params, result ? result : &tmp, workspace, static_cast<hipStream_t>(stream));
+    SS4_GUARD_END
+}
+
+int subsurf4d_copy_probe(const void* src, void* dst, size_t bytes, int32_t reps, double* ms, void* stream)
+{
+    SS4_GUARD_BEGIN
+    g_error.clear();
+    if (!src || !dst || !ms || reps < 1) return fail(SUBSURF4D_EINVAL, "bad arguments");
+    if (bytes == 0 || bytes % 16 != 0) return fail(SUBSURF4D_EINVAL, "bytes must be a positive multiple of 16");
+    if (reinterpret_cast<uintptr_t>(src) % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0)
+        return fail(SUBSURF4D_EINVAL, "buffers must be 16-byte aligned");
+    return run_copy_probe(src, dst, bytes, reps, ms, static_cast<hipStream_t>(stream));
     SS4_GUARD_END
 }
 

@@ -13,7 +13,7 @@ namespace ss4 {
 
 constexpr int kBlock = 256;     // threads per block (4 wave64s)
 constexpr int kXcd = 8;         // MI355X: 8 XCDs, blocks are dealt round-robin
-constexpr int kGridCap = 4096;  // persistent-style grid cap (multiple of kXcd)
+constexpr int kGridCap = 8192;  // persistent-style grid cap (multiple of kXcd)
 
 // ---------------------------------------------------------------- layouts
 //
@@ -39,8 +39,19 @@ struct Layout {
     int64_t nrow_int;       // n2*n3*n4
     int64_t npad, nint;     // padded / interior cell counts
     int64_t usplit;         // elements of one colour buffer of u
-    int64_t csplit;         // elements of one colour of one coefficient array
+    int64_t csplit;         // elements of one colour of one coefficient array (row layout)
+    int ntm;                // coefficient tiles (kTileSlots slots) per row
+    int64_t cblk;           // values of one colour in the tiled coefficient block
 };
+
+// Tiled coefficient block of one colour: for every interior row and 64-slot
+// tile, 9 fields (the 8 face coefficients in face order -x,+x,-y,+y,-z,+z,-t,+t,
+// then the right-hand side) of 128 slots each, contiguous.  A wave that
+// updates one tile reads one 9 KB run instead of nine streams.
+constexpr int kTileShift = 7;
+constexpr int kTileSlots = 1 << kTileShift;   // 128 slots
+constexpr int kTileFields = 9;
+constexpr int kTileVals = kTileFields * kTileSlots;
 
 inline Layout make_layout(const int32_t n[4])
 {
@@ -49,8 +60,8 @@ inline Layout make_layout(const int32_t n[4])
     L.p1 = n[0] + 2; L.p2 = n[1] + 2; L.p3 = n[2] + 2; L.p4 = n[3] + 2;
     L.half = (n[0] + 1) / 2;
     const bool wide = L.half >= 64;
-    L.xoff = wide ? 8 : 1;                       // 64-byte aligned interior for wide rows
-    const int need = L.xoff + n[0] / 2 + 1;      // slots m = -1 .. N1>>1
+    L.xoff = wide ? 16 : 1;                      // 128-byte aligned interior for wide rows
+    const int need = L.xoff + n[0] / 2 + 2;      // slots m = -1 .. N1>>1, +1 for pair loads
     const int align = wide ? 16 : 2;
     L.rs = (need + align - 1) / align * align;
     L.rsc = wide ? (L.half + 15) / 16 * 16 : L.half;
@@ -60,7 +71,16 @@ inline Layout make_layout(const int32_t n[4])
     L.nint = (int64_t)n[0] * L.nrow_int;
     L.usplit = L.nrow_pad * L.rs;
     L.csplit = L.nrow_int * L.rsc;
+    L.ntm = (L.half + kTileSlots - 1) / kTileSlots;
+    L.cblk = L.nrow_int * L.ntm * kTileVals;
     return L;
+}
+
+// Index of field 0 of slot m in interior row r of colour `colour` in the tiled
+// coefficient block; field f is at +f*kTileSlots.
+__host__ __device__ __forceinline__ int64_t ctile(const Layout& L, int colour, int64_t r, int m)
+{
+    return (((int64_t)colour * L.nrow_int + r) * L.ntm + (m >> kTileShift)) * kTileVals + (m & (kTileSlots - 1));
 }
 
 // ------------------------------------------------------- device control block

@@ -14,6 +14,7 @@ struct WsPlan {
     Layout L;
     int32_t n_centres = 0;
     int32_t precision = 0;
+    int64_t max_grid = 0;    // entries of each per-block partial array
     size_t ctrl = 0, part_a = 0, part_b = 0, balls = 0, big = 0;
     // time step
     size_t ured0 = 0, ured1 = 0, ublack = 0, coef = 0, rhs = 0;
@@ -46,6 +47,11 @@ int hip_fail(hipError_t e, const char* what);
         if (e_ != hipSuccess) return ss4::hip_fail(e_, what); \
     } while (0)
 
+// Largest grid whose blocks are all resident at once on the current device
+// (occupancy x compute units, a multiple of kXcd, at most kGridCap), so a
+// grid-stride kernel never runs a partial second round of blocks.
+int resident_grid(const void* kernel);
+
 // preparation (prepare.hip)
 int run_prepare(const WsPlan& P, double h, const void* image, int dtype,
                 const subsurf4d_centre* centres, int nc, const subsurf4d_prepare_params& pp,
@@ -68,6 +74,7 @@ int run_solve(const WsPlan& P, const double* coef, const double* b, double* u,
 int run_sor_loop(const WsPlan& P, const subsurf4d_step_params& sp, void* ws, hipStream_t s,
                  subsurf4d_result* res);
 int run_unsplit(const WsPlan& P, double* u, void* ws, hipStream_t s);
+int run_copy_probe(const void* src, void* dst, size_t bytes, int reps, double* ms, hipStream_t s);
 
 // mixed precision (mixed.hip)
 int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,

@@ -3,6 +3,7 @@
 // A_eps and A_eps-bar), red-black SOR half-sweeps with the residual norm fused
 // in, and the host driver of the iteration.
 #include <cmath>
+#include <cstdlib>
 
 #include "ss4_internal.hpp"
 
@@ -22,8 +23,7 @@ struct AsmArgs {
     double* ured0;
     double* ured1;
     double* ublack;
-    double* coef;     // 16 arrays of csplit: [colour*8 + face]
-    double* rhs;      // 2 arrays of csplit
+    double* coef;     // tiled coefficient + rhs block, both colours
     double* coef_nat; // interior x 8
     double* b_nat;    // interior
     double* part_a;
@@ -114,10 +114,10 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
         acc_r += r0 * r0;
         const int64_t irow = ((int64_t)(l - 1) * L.n3 + (k - 1)) * L.n2 + (j - 1);
         if (MODE == kSplit) {
-            const int64_t ci = irow * L.rsc + m;
+            const int64_t ci = ctile(L, colour, irow, m);
 #pragma unroll
-            for (int f = 0; f < 8; ++f) a.coef[(int64_t)(colour * 8 + f) * L.csplit + ci] = c[f];
-            a.rhs[(int64_t)colour * L.csplit + ci] = w0;
+            for (int f = 0; f < 8; ++f) a.coef[ci + f * kTileSlots] = c[f];
+            a.coef[ci + 8 * kTileSlots] = w0;
         } else {
             const int64_t qi = irow * L.n1 + (i - 1);
 #pragma unroll
@@ -150,8 +150,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
 // the colour-split arrays; ghost slots of u are 0 so they contribute nothing.
 __global__ __launch_bounds__(kBlock) void k_load_system(Layout L, const double* coef_nat, const double* b_nat,
                                                          const double* u, double* ured0, double* ured1,
-                                                         double* ublack, double* coef, double* rhs,
-                                                         double* part_a, double* part_b, Ctrl* C)
+                                                         double* ublack, double* coef, double* part_a,
+                                                         double* part_b, Ctrl* C)
 {
     __shared__ double lds[4];
     __shared__ int flag;
@@ -176,19 +176,19 @@ __global__ __launch_bounds__(kBlock) void k_load_system(Layout L, const double* 
         const int nn[4] = {L.n1, L.n2, L.n3, L.n4};
         const int64_t irow = ((int64_t)(l - 1) * L.n3 + (k - 1)) * L.n2 + (j - 1);
         const int64_t qi = irow * L.n1 + (i - 1);
-        const int64_t ci = irow * L.rsc + m;
+        const int64_t ci = ctile(L, colour, irow, m);
         double D = 1.0, s = b_nat[qi];
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             const double cm = coef_nat[qi * 8 + 2 * d], cp = coef_nat[qi * 8 + 2 * d + 1];
-            coef[(int64_t)(colour * 8 + 2 * d) * L.csplit + ci] = cm;
-            coef[(int64_t)(colour * 8 + 2 * d + 1) * L.csplit + ci] = cp;
+            coef[ci + (2 * d) * kTileSlots] = cm;
+            coef[ci + (2 * d + 1) * kTileSlots] = cp;
             D += cm;
             D += cp;
             if (idx[d] > 1) s += cm * u[p - sd[d]];
             if (idx[d] < nn[d]) s += cp * u[p + sd[d]];
         }
-        rhs[(int64_t)colour * L.csplit + ci] = b_nat[qi];
+        coef[ci + 8 * kTileSlots] = b_nat[qi];
         const double r0 = s - D * v;
         acc_b += b_nat[qi] * b_nat[qi];
         acc_r += r0 * r0;
@@ -217,8 +217,7 @@ struct SweepArgs {
     const double* uin;    // own colour, iterate k-1
     double* uout;         // own colour, iterate k (== uin for black)
     const double* uoth;   // other colour
-    const double* coef;   // 8 arrays of csplit for this colour
-    const double* rhs;    // this colour
+    const double* coef;   // tiled coefficient + rhs block (both colours)
     double omega;
     double* part;         // this kernel's per-block partials
     const double* part_other;  // black partials of iterate k-1 (red check)
@@ -226,6 +225,84 @@ struct SweepArgs {
     int k;                // iteration number
     int check;            // red: test the stopping rule for iterate k-1
 };
+
+// Streaming accesses for data a sweep touches once (coefficients, rhs, own
+// colour): non-temporal, so the neighbour rows of the other colour, which
+// several blocks read, keep their place in L2.  Compile-time switch kept for
+// measurement: SS4_STREAMING=0 gives plain accesses.
+#ifndef SS4_STREAMING
+#define SS4_STREAMING 1
+#endif
+__device__ __forceinline__ double ld_stream(const double* p)
+{
+#if SS4_STREAMING
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+__device__ __forceinline__ void st_stream(double* p, double v)
+{
+#if SS4_STREAMING
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ dvec2 ld2(const double* p) { return *reinterpret_cast<const dvec2*>(p); }
+
+__device__ __forceinline__ dvec2 ld2_stream(const double* p)
+{
+#if SS4_STREAMING
+    return __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(p));
+#else
+    return *reinterpret_cast<const dvec2*>(p);
+#endif
+}
+
+__device__ __forceinline__ void st2_stream(double* p, dvec2 v)
+{
+#if SS4_STREAMING
+    __builtin_nontemporal_store(v, reinterpret_cast<dvec2*>(p));
+#else
+    *reinterpret_cast<dvec2*>(p) = v;
+#endif
+}
+
+// End of a half-sweep: per-block partial of the squared residual rows; for a
+// checking red sweep the last block adds the black partials of the same
+// iterate and applies the stopping rule to iterate k-1.
+template <int COLOR>
+__device__ __forceinline__ void finish_sweep(const SweepArgs& a, double acc, double* lds, int* flag)
+{
+    Ctrl* C = a.C;
+    const double bs = block_sum(acc, lds);
+    if (threadIdx.x == 0) a.part[blockIdx.x] = bs;
+    if (COLOR == 1 || !a.check) return;
+    if (!arrive_last(&C->arrive[1], gridDim.x, flag)) return;
+    const double Rr = sum_partials(a.part, gridDim.x, lds);
+    const double Rb = sum_partials(a.part_other, gridDim.x, lds);
+    if (threadIdx.x == 0) {
+        const int kk = a.k - 1;
+        const double R2 = Rb + Rr;
+        const double R = sqrt(R2);
+        C->rel_res = C->bn > 0.0 ? R / C->bn : R;
+        bool stop = true;
+        if (!(R2 < INFINITY)) C->status = SUBSURF4D_ENONFINITE;
+        else if (R <= C->tol * C->bn) C->status = SUBSURF4D_OK;
+        else if (kk >= C->max_iter) C->status = SUBSURF4D_NOT_CONVERGED;
+        else stop = false;
+        if (stop) {
+            C->done = 1;
+            C->iterations = kk;
+            C->final_red = kk & 1;
+        }
+        C->arrive[1] = 0;
+    }
+}
 
 // Half-sweep of colour COLOR (0 = red, 1 = black).  Tile = 64 slots of one row
 // per wave, 4 rows per block.  Each cell: ubar = (b + sum_f c_f u_f)/D,
@@ -244,7 +321,6 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a)
     const int ntm = (L.half + 63) >> 6;
     const int64_t ntr = (L.nrow_int + 3) >> 2;
     const int64_t sy = L.rs, sz = (int64_t)L.p2 * L.rs, st = (int64_t)L.p2 * L.p3 * L.rs;
-    const int64_t cs = L.csplit;
     const double om = a.omega, om1 = 1.0 - a.omega;
     double acc = 0.0;
     for (TileWalk tw(ntm * ntr); tw.t < tw.end; tw.t += tw.step) {
@@ -262,50 +338,206 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs a)
         if (m >= cnt) continue;
         const int64_t prow = ((int64_t)l * L.p3 + k) * L.p2 + j;
         const int64_t ui = prow * L.rs + L.xoff + m;
-        const int64_t ci = r * L.rsc + m;
-        const double c0 = a.coef[ci], c1 = a.coef[cs + ci], c2 = a.coef[2 * cs + ci], c3 = a.coef[3 * cs + ci];
-        const double c4 = a.coef[4 * cs + ci], c5 = a.coef[5 * cs + ci], c6 = a.coef[6 * cs + ci], c7 = a.coef[7 * cs + ci];
+        const double* cf = a.coef + ctile(L, COLOR, r, m);
+        const double c0 = ld_stream(cf), c1 = ld_stream(cf + kTileSlots), c2 = ld_stream(cf + 2 * kTileSlots);
+        const double c3 = ld_stream(cf + 3 * kTileSlots), c4 = ld_stream(cf + 4 * kTileSlots);
+        const double c5 = ld_stream(cf + 5 * kTileSlots), c6 = ld_stream(cf + 6 * kTileSlots);
+        const double c7 = ld_stream(cf + 7 * kTileSlots);
         const double* uo = a.uoth;
-        double s = a.rhs[ci];
+        double s = ld_stream(cf + 8 * kTileSlots);
         s += c0 * uo[ui - par] + c1 * uo[ui + 1 - par];
         s += c2 * uo[ui - sy] + c3 * uo[ui + sy];
         s += c4 * uo[ui - sz] + c5 * uo[ui + sz];
         s += c6 * uo[ui - st] + c7 * uo[ui + st];
         const double D = ((((((((1.0 + c0) + c1) + c2) + c3) + c4) + c5) + c6) + c7);
         const double ub = s / D;
-        const double uold = a.uin[ui];
-        a.uout[ui] = om * ub + om1 * uold;
+        const double uold = ld_stream(a.uin + ui);
+        st_stream(a.uout + ui, om * ub + om1 * uold);
         const double rres = COLOR == 0 ? D * (ub - uold) : D * om1 * (ub - uold);
         acc += rres * rres;
     }
-    const double bs = block_sum(acc, lds);
-    if (threadIdx.x == 0) a.part[blockIdx.x] = bs;
-    if (COLOR == 1 || !a.check) return;
-    if (!arrive_last(&C->arrive[1], gridDim.x, &flag)) return;
-    const double Rr = sum_partials(a.part, gridDim.x, lds);
-    const double Rb = sum_partials(a.part_other, gridDim.x, lds);
-    if (threadIdx.x == 0) {
-        const int kk = a.k - 1;
-        const double R2 = Rb + Rr;
-        const double R = sqrt(R2);
-        C->rel_res = C->bn > 0.0 ? R / C->bn : R;
-        if (!(R2 < INFINITY)) {
-            C->status = SUBSURF4D_ENONFINITE;
-            C->done = 1;
-            C->iterations = kk;
-            C->final_red = kk & 1;
-        } else if (R <= C->tol * C->bn) {
-            C->done = 1;
-            C->iterations = kk;
-            C->final_red = kk & 1;
-        } else if (kk >= C->max_iter) {
-            C->status = SUBSURF4D_NOT_CONVERGED;
-            C->done = 1;
-            C->iterations = kk;
-            C->final_red = kk & 1;
+    finish_sweep<COLOR>(a, acc, lds, &flag);
+}
+
+// Half-sweep in "t-marching" form.  A block owns a column tile (64 slots x 4
+// y-rows at one z) and walks through the frames l = 1..N4.  Each thread keeps
+// the other colour's values of its slot at l-1, l, l+1 in registers: they are
+// its t-neighbours and one of its x-neighbours; the other x-neighbour comes
+// from the adjacent lane.  y and z neighbours are read through the caches;
+// column tiles are dealt k-fastest to the blocks of each XCD, so the blocks
+// resident together share their z neighbours in L2.  Same arithmetic as
+// k_sweep (the red-black iterate does not depend on the visiting order).
+template <int COLOR>
+__global__ __launch_bounds__(kBlock) void k_sweep_tm(SweepArgs a)
+{
+    __shared__ double lds[4];
+    __shared__ int flag;
+    Ctrl* C = a.C;
+    if (C->done) return;
+    const Layout& L = a.L;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int ntm = (L.half + 63) >> 6;
+    const int njb = (L.n2 + 3) >> 2;
+    const int64_t ncol = (int64_t)ntm * njb * L.n3;
+    const int64_t sy = L.rs, sz = (int64_t)L.p2 * L.rs, st = (int64_t)L.p2 * L.p3 * L.rs;
+    const int64_t cst = (int64_t)L.n2 * L.n3 * L.ntm * kTileVals;   // coefficient stride between frames
+    const int last_slot = L.n1 >> 1;                     // highest slot holding data in a row
+    const double om = a.omega, om1 = 1.0 - a.omega;
+    const double* __restrict__ uo = a.uoth;
+    double acc = 0.0;
+    for (TileWalk tw(ncol); tw.t < tw.end; tw.t += tw.step) {
+        const int k = (int)(tw.t % L.n3) + 1;
+        const int64_t t2 = tw.t / L.n3;
+        const int jb = (int)(t2 % njb);
+        const int mt = (int)(t2 / njb);
+        const int j = jb * 4 + ty + 1;
+        const int m = mt * 64 + tx;
+        const bool jok = j <= L.n2;                      // uniform across the wave
+        const bool sok = jok && m <= last_slot;
+        const int64_t ub = ((int64_t)k * L.p2 + j) * L.rs + L.xoff + m;      // row (j,k,l=0)
+        const int64_t cb = ctile(L, COLOR, ((int64_t)(k - 1) * L.n2 + (j - 1)), m);  // row (j,k,l=1)
+        double Bm = sok ? uo[ub] : 0.0;
+        double Bc = sok ? uo[ub + st] : 0.0;
+        for (int l = 1; l <= L.n4; ++l) {
+            const int64_t ui = ub + (int64_t)l * st;
+            const double Bp = sok ? uo[ui + st] : 0.0;
+            const int par = (COLOR + j + k + l) & 1;
+            double left = __shfl_up(Bc, 1);
+            double right = __shfl_down(Bc, 1);
+            if (jok) {
+                if (tx == 0 && par) left = uo[ui - 1];
+                if (tx == 63 && !par && m + 1 <= last_slot) right = uo[ui + 1];
+                const int cnt = par ? (L.n1 + 1) >> 1 : L.n1 >> 1;
+                if (m < cnt) {
+                    const double* cf = a.coef + cb + (int64_t)(l - 1) * cst;
+                    const double c0 = ld_stream(cf), c1 = ld_stream(cf + kTileSlots);
+                    const double c2 = ld_stream(cf + 2 * kTileSlots), c3 = ld_stream(cf + 3 * kTileSlots);
+                    const double c4 = ld_stream(cf + 4 * kTileSlots), c5 = ld_stream(cf + 5 * kTileSlots);
+                    const double c6 = ld_stream(cf + 6 * kTileSlots), c7 = ld_stream(cf + 7 * kTileSlots);
+                    const double xl = par ? left : Bc;
+                    const double xr = par ? Bc : right;
+                    double s = ld_stream(cf + 8 * kTileSlots);
+                    s += c0 * xl + c1 * xr;
+                    s += c2 * uo[ui - sy] + c3 * uo[ui + sy];
+                    s += c4 * uo[ui - sz] + c5 * uo[ui + sz];
+                    s += c6 * Bm + c7 * Bp;
+                    const double D = ((((((((1.0 + c0) + c1) + c2) + c3) + c4) + c5) + c6) + c7);
+                    const double ubar = s / D;
+                    const double uold = ld_stream(a.uin + ui);
+                    st_stream(a.uout + ui, om * ubar + om1 * uold);
+                    const double rres = COLOR == 0 ? D * (ubar - uold) : D * om1 * (ubar - uold);
+                    acc += rres * rres;
+                }
+            }
+            Bm = Bc;
+            Bc = Bp;
         }
-        C->arrive[1] = 0;
     }
+    finish_sweep<COLOR>(a, acc, lds, &flag);
+}
+
+// Half-sweep, frame-marching with two cells per lane (rows of >= 64 slots,
+// whose u rows are 128-byte aligned): a wave covers one 128-slot coefficient
+// tile of one row, lane t owns slots m = 2t, 2t+1, and every stream moves 16
+// bytes per lane.  One block per column tile (128 slots x 4 y-rows at one z),
+// marching over the frames; blocks are mapped so that each XCD processes a
+// contiguous, k-fastest range of column tiles (shared z neighbours in L2).
+template <int COLOR>
+__global__ __launch_bounds__(kBlock) void k_sweep_t2(SweepArgs a)
+{
+    __shared__ double lds[4];
+    __shared__ int flag;
+    Ctrl* C = a.C;
+    if (C->done) return;
+    const Layout& L = a.L;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int njb = (L.n2 + 3) >> 2;
+    const int64_t ncol = (int64_t)L.ntm * njb * L.n3;
+    const int64_t per_xcd = (ncol + kXcd - 1) / kXcd;
+    const int64_t t = (int64_t)(blockIdx.x % kXcd) * per_xcd + blockIdx.x / kXcd;
+    const int64_t sy = L.rs, sz = (int64_t)L.p2 * L.rs, st = (int64_t)L.p2 * L.p3 * L.rs;
+    const int64_t cst = (int64_t)L.n2 * L.n3 * L.ntm * kTileVals;
+    const int last_slot = L.n1 >> 1;
+    const double om = a.omega, om1 = 1.0 - a.omega;
+    const double* __restrict__ uo = a.uoth;
+    double acc = 0.0;
+    if (t < ncol) {
+        const int k = (int)(t % L.n3) + 1;
+        const int64_t t2 = t / L.n3;
+        const int jb = (int)(t2 % njb);
+        const int mt = (int)(t2 / njb);
+        const int j = jb * 4 + ty + 1;
+        const int m = mt * kTileSlots + 2 * tx;
+        const bool jok = j <= L.n2;                      // uniform across the wave
+        const bool sok = jok && m <= last_slot;
+        const int64_t ub = ((int64_t)k * L.p2 + j) * L.rs + L.xoff + m;
+        const int64_t cb = ctile(L, COLOR, ((int64_t)(k - 1) * L.n2 + (j - 1)), m);
+        const dvec2 zero2 = {0.0, 0.0};
+        dvec2 Bm = sok ? ld2(uo + ub) : zero2;
+        dvec2 Bc = sok ? ld2(uo + ub + st) : zero2;
+        for (int l = 1; l <= L.n4; ++l) {
+            const int64_t ui = ub + (int64_t)l * st;
+            const dvec2 Bp = sok ? ld2(uo + ui + st) : zero2;
+            const int par = (COLOR + j + k + l) & 1;
+            double left = __shfl_up(Bc.y, 1);
+            double right = __shfl_down(Bc.x, 1);
+            if (jok) {
+                if (tx == 0 && par) left = uo[ui - 1];
+                if (tx == 63 && !par && m + 2 <= last_slot) right = uo[ui + 2];
+                const int cnt = par ? (L.n1 + 1) >> 1 : L.n1 >> 1;
+                if (m < cnt) {
+                    const bool a1 = m + 1 < cnt;
+                    const double* cf = a.coef + cb + (int64_t)(l - 1) * cst;
+                    const dvec2 c0 = ld2_stream(cf), c1 = ld2_stream(cf + kTileSlots);
+                    const dvec2 c2 = ld2_stream(cf + 2 * kTileSlots), c3 = ld2_stream(cf + 3 * kTileSlots);
+                    const dvec2 c4 = ld2_stream(cf + 4 * kTileSlots), c5 = ld2_stream(cf + 5 * kTileSlots);
+                    const dvec2 c6 = ld2_stream(cf + 6 * kTileSlots), c7 = ld2_stream(cf + 7 * kTileSlots);
+                    const dvec2 bb = ld2_stream(cf + 8 * kTileSlots);
+                    const dvec2 ym = ld2(uo + ui - sy), yp = ld2(uo + ui + sy);
+                    const dvec2 zm = ld2(uo + ui - sz), zp = ld2(uo + ui + sz);
+                    const dvec2 uold = ld2_stream(a.uin + ui);
+                    // cell m: x-neighbours (m-par, m+1-par); cell m+1: (m+1-par, m+2-par)
+                    const double xl0 = par ? left : Bc.x, xr0 = par ? Bc.x : Bc.y;
+                    const double xl1 = par ? Bc.x : Bc.y, xr1 = par ? Bc.y : right;
+                    double s0 = bb.x, s1 = bb.y;
+                    s0 += c0.x * xl0 + c1.x * xr0;
+                    s1 += c0.y * xl1 + c1.y * xr1;
+                    s0 += c2.x * ym.x + c3.x * yp.x;
+                    s1 += c2.y * ym.y + c3.y * yp.y;
+                    s0 += c4.x * zm.x + c5.x * zp.x;
+                    s1 += c4.y * zm.y + c5.y * zp.y;
+                    s0 += c6.x * Bm.x + c7.x * Bp.x;
+                    s1 += c6.y * Bm.y + c7.y * Bp.y;
+                    const double D0 = ((((((((1.0 + c0.x) + c1.x) + c2.x) + c3.x) + c4.x) + c5.x) + c6.x) + c7.x);
+                    const double D1 = ((((((((1.0 + c0.y) + c1.y) + c2.y) + c3.y) + c4.y) + c5.y) + c6.y) + c7.y);
+                    const double ub0 = s0 / D0, ub1 = s1 / D1;
+                    const double n0 = om * ub0 + om1 * uold.x;
+                    const double n1 = om * ub1 + om1 * uold.y;
+                    if (a1) {
+                        const dvec2 nv = {n0, n1};
+                        st2_stream(a.uout + ui, nv);
+                    } else {
+                        st_stream(a.uout + ui, n0);
+                    }
+                    const double r0 = COLOR == 0 ? D0 * (ub0 - uold.x) : D0 * om1 * (ub0 - uold.x);
+                    const double r1 = COLOR == 0 ? D1 * (ub1 - uold.y) : D1 * om1 * (ub1 - uold.y);
+                    acc += r0 * r0;
+                    if (a1) acc += r1 * r1;
+                }
+            }
+            Bm = Bc;
+            Bc = Bp;
+        }
+    }
+    finish_sweep<COLOR>(a, acc, lds, &flag);
+}
+
+// Plain 16-byte copy (bandwidth probe and counter calibration).
+__global__ __launch_bounds__(kBlock) void k_copy_probe(const double2* __restrict__ src, double2* __restrict__ dst,
+                                                       int64_t n)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        dst[q] = src[q];
 }
 
 // colour-split u -> interior of the padded u
@@ -327,10 +559,36 @@ __global__ __launch_bounds__(kBlock) void k_unsplit(Layout L, const double* ured
     }
 }
 
-int sweep_grid(const Layout& L)
+int sweep_grid(const Layout& L, int variant)
 {
-    const int64_t ntiles = (int64_t)((L.half + 63) >> 6) * ((L.nrow_int + 3) >> 2);
-    return grid_for(ntiles, 1);
+    int64_t work;
+    int res;
+    if (variant == 2) {
+        const int64_t ncol = (int64_t)L.ntm * ((L.n2 + 3) >> 2) * L.n3;
+        return (int)((ncol + kXcd - 1) / kXcd * kXcd);
+    }
+    if (variant == 1) {
+        work = (int64_t)L.ntm * ((L.n2 + 3) >> 2) * L.n3;
+        res = resident_grid(reinterpret_cast<const void*>(&k_sweep_tm<0>));
+    } else {
+        work = (int64_t)L.ntm * ((L.nrow_int + 3) >> 2);
+        res = resident_grid(reinterpret_cast<const void*>(&k_sweep<0>));
+    }
+    const int64_t g = work < res ? work : res;
+    return (int)((g + kXcd - 1) / kXcd * kXcd);
+}
+
+// Sweep kernel choice.  1 (default): frame-marching columns (k_sweep_tm), the
+// fastest measured on the config-2 volume; 0: row tiles (k_sweep); 2: marching
+// with two cells per lane (k_sweep_t2, wide rows only).  SUBSURF4D_SWEEP=r|t|p
+// selects one explicitly (all three give the same iterates).
+int sweep_variant(const Layout& L)
+{
+    const bool wide = L.half >= 64;   // 128-byte aligned u rows, pairs stay in the row
+    static const char* env = getenv("SUBSURF4D_SWEEP");
+    if (env && env[0] == 'r') return 0;
+    if (env && env[0] == 'p' && wide) return 2;
+    return 1;
 }
 
 void fill_result(const Ctrl& hc, subsurf4d_result* res)
@@ -360,23 +618,21 @@ int run_sor_loop(const WsPlan& P, const subsurf4d_step_params& sp, void* ws, hip
     double* ured[2] = {ws_ptr<double>(ws, P.ured0), ws_ptr<double>(ws, P.ured1)};
     double* ublack = ws_ptr<double>(ws, P.ublack);
     const double* coef = ws_ptr<double>(ws, P.coef);
-    const double* rhs = ws_ptr<double>(ws, P.rhs);
     double* pa = ws_ptr<double>(ws, P.part_a);
     double* pb = ws_ptr<double>(ws, P.part_b);
     double tol;
     int max_iter;
     effective_stop(sp, &tol, &max_iter);
     const int check_every = sp.check_every > 0 ? sp.check_every : 1;
-    const int grid = sweep_grid(L);
+    const int variant = sweep_variant(L);
+    const int grid = sweep_grid(L, variant);
 
     SweepArgs red{}, black{};
     red.L = black.L = L;
     red.omega = black.omega = sp.omega;
     red.C = black.C = C;
     red.coef = coef;
-    red.rhs = rhs;
-    black.coef = coef + 8 * L.csplit;
-    black.rhs = rhs + L.csplit;
+    black.coef = coef;
     red.part = pa;
     red.part_other = pb;
     black.part = pb;
@@ -396,11 +652,15 @@ int run_sor_loop(const WsPlan& P, const subsurf4d_step_params& sp, void* ws, hip
             red.uin = ured[(k - 1) & 1];
             red.uout = ured[k & 1];
             red.check = (k >= 2) && (((k - 1) % check_every == 0) || (k - 1 >= max_iter));
-            k_sweep<0><<<grid, kBlock, 0, s>>>(red);
+            if (variant == 2) k_sweep_t2<0><<<grid, kBlock, 0, s>>>(red);
+            else if (variant == 1) k_sweep_tm<0><<<grid, kBlock, 0, s>>>(red);
+            else k_sweep<0><<<grid, kBlock, 0, s>>>(red);
             if (k <= max_iter) {
                 black.k = k;
                 black.uoth = ured[k & 1];
-                k_sweep<1><<<grid, kBlock, 0, s>>>(black);
+                if (variant == 2) k_sweep_t2<1><<<grid, kBlock, 0, s>>>(black);
+                else if (variant == 1) k_sweep_tm<1><<<grid, kBlock, 0, s>>>(black);
+                else k_sweep<1><<<grid, kBlock, 0, s>>>(black);
             }
         }
         SS4_LAUNCHED("sweeps");
@@ -422,6 +682,28 @@ int run_sor_loop(const WsPlan& P, const subsurf4d_step_params& sp, void* ws, hip
         set_error("non-finite residual in the SOR solve");
         return SUBSURF4D_ENONFINITE;
     }
+    return 0;
+}
+
+int run_copy_probe(const void* src, void* dst, size_t bytes, int reps, double* ms, hipStream_t s)
+{
+    const int64_t n = (int64_t)(bytes / 16);
+    hipEvent_t a, b;
+    SS4_HIP(hipEventCreate(&a));
+    SS4_HIP(hipEventCreate(&b));
+    const int grid = 8192;
+    k_copy_probe<<<grid, kBlock, 0, s>>>(static_cast<const double2*>(src), static_cast<double2*>(dst), n);
+    SS4_HIP(hipEventRecord(a, s));
+    for (int r = 0; r < reps; ++r)
+        k_copy_probe<<<grid, kBlock, 0, s>>>(static_cast<const double2*>(src), static_cast<double2*>(dst), n);
+    SS4_HIP(hipEventRecord(b, s));
+    SS4_HIP(hipEventSynchronize(b));
+    float t = 0.f;
+    SS4_HIP(hipEventElapsedTime(&t, a, b));
+    *ms = (double)t / reps;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    SS4_LAUNCHED("copy probe");
     return 0;
 }
 
@@ -477,7 +759,6 @@ int run_step(const WsPlan& P, double h, const double* G, const subsurf4d_centre*
         a.ured1 = ws_ptr<double>(ws, P.ured1);
         a.ublack = ws_ptr<double>(ws, P.ublack);
         a.coef = ws_ptr<double>(ws, P.coef);
-        a.rhs = ws_ptr<double>(ws, P.rhs);
         a.part_a = ws_ptr<double>(ws, P.part_a);
         a.part_b = ws_ptr<double>(ws, P.part_b);
         a.C = C;
@@ -507,8 +788,8 @@ int run_solve(const WsPlan& P, const double* coef, const double* b, double* u,
     k_ctrl_init<<<1, 64, 0, s>>>(C, tol, max_iter);
     k_load_system<<<grid_for(L.npad), kBlock, 0, s>>>(L, coef, b, u, ws_ptr<double>(ws, P.ured0),
                                                       ws_ptr<double>(ws, P.ured1), ws_ptr<double>(ws, P.ublack),
-                                                      ws_ptr<double>(ws, P.coef), ws_ptr<double>(ws, P.rhs),
-                                                      ws_ptr<double>(ws, P.part_a), ws_ptr<double>(ws, P.part_b), C);
+                                                      ws_ptr<double>(ws, P.coef), ws_ptr<double>(ws, P.part_a),
+                                                      ws_ptr<double>(ws, P.part_b), C);
     SS4_LAUNCHED("load system");
     int rc = run_sor_loop(P, sp, ws, s, res);
     if (rc < 0) return rc;
