@@ -108,6 +108,9 @@ def main():
     ap.add_argument("--frames", type=int, default=16, help="t extent (16 = full workload)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mixed-steps", type=int, default=-1,
+                    help="also time this many steps with the mixed-precision solve (-1: same as --steps)")
+    ap.add_argument("--inner", type=int, default=20, help="FP32 sweeps per refinement pass (mixed)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -134,7 +137,7 @@ def main():
     pp = B.PrepareParams(image_scale=1.0 / 255.0)
     sp = B.StepParams(omega=1.8)
 
-    job = B.Job(n, img.image, img.centres, img.seeds)
+    job = B.Job(n, img.image, img.centres, img.seeds, precision=B.MIXED)
     t0 = time.perf_counter()
     rc = job.prepare(pp)
     job.init(v=1.0, R=8.0, ball_r=sp.ball_r)
@@ -197,6 +200,40 @@ def main():
     if ct is not None:
         out["roofline"]["traffic"] = ct["hbm_bytes_per_launch"]
         out["roofline"]["traffic_source"] = COUNTER_SUMMARY
+    mixed_steps = args.steps if args.mixed_steps < 0 else args.mixed_steps
+    if mixed_steps > 0:
+        # same job from the same initial function: mixed-precision solve of every step
+        # (FP32 red-black sweeps on BF16 coefficients, FP64 refinement to the FP64
+        # stopping rule tol=1e-8, and to 1e-10 as configured for the mixed workload)
+        from dataclasses import replace
+        for tol_name, rtol in (("tol_1e-8", 1e-8), ("tol_1e-10", 1e-10)):
+            msp = replace(sp, precision=B.MIXED, refine_tol=rtol, inner_sweeps=args.inner)
+            job.init(v=1.0, R=8.0, ball_r=sp.ball_r)
+            for w in range(args.warmup):
+                job.step(msp)
+            B.timing(1)
+            B.timing(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            recs = [job.step(msp) for _ in range(mixed_steps)]
+            torch.cuda.synchronize()
+            mdt = time.perf_counter() - t0
+            mt = B.timing(3)
+            B.timing(0)
+            mlaunch = mt["sweep_ms"] / max(mt["sweep_launches"], 1)
+            mbytes = 32.0 * cells / 2.0
+            out.setdefault("mixed", {})[tol_name] = {
+                "ms_per_step": mdt * 1e3 / mixed_steps,
+                "speedup_vs_fp64_step": (dt / args.steps) / (mdt / mixed_steps),
+                "refinement_passes": [r["outer"] for r in recs],
+                "inner_sweeps_per_pass": args.inner,
+                "final_rel_residual": [r["rel_res"] for r in recs],
+                "inner_sweep_avg_launch_ms": mlaunch,
+                "inner_sweep_GBs_algorithmic": mbytes / (mlaunch * 1e-3) / 1e9,
+                "inner_bytes_per_update": 32,
+            }
+            log(f"[bench] mixed {tol_name}: {mdt * 1e3 / mixed_steps:.1f} ms/step, passes "
+                f"{[r['outer'] for r in recs]}, inner sweep {mbytes / (mlaunch * 1e-3) / 1e9:.0f} GB/s")
     # practical HBM bandwidth of a plain 16-byte copy (4 GiB read + 4 GiB written)
     nb = 1 << 32
     src = torch.empty(nb, dtype=torch.uint8, device="cuda")

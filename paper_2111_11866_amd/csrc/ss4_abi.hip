@@ -88,13 +88,11 @@ bool plan_workspace(const int32_t n[4], int32_t n_centres, int32_t precision, Ws
     P->ublack = s; s += align256(sizeof(double) * L.usplit);
     P->coef = s; s += align256(sizeof(double) * 2 * L.cblk);     // coefficients + rhs, tiled
     if (precision == SUBSURF4D_MIXED) {
-        P->xf64 = s; s += align256(sizeof(double) * L.npad);          // FP64 iterate (padded)
-        P->rf32 = s; s += align256(sizeof(float) * 2 * L.csplit);     // FP32 residual, split
-        P->dred0 = s; s += align256(sizeof(float) * L.usplit);        // FP32 correction, split
-        P->dred1 = s; s += align256(sizeof(float) * L.usplit);
+        const int64_t recs = 2 * L.nrow_int * L.ntm * kTileSlots;      // both colours
+        P->coef16 = s; s += align256(16 * (size_t)recs);                 // 8 x BF16 per cell
+        P->rf32 = s; s += align256(sizeof(float) * (size_t)recs);        // scaled FP32 residual
+        P->dred = s; s += align256(sizeof(float) * L.usplit);            // FP32 correction, split
         P->dblack = s; s += align256(sizeof(float) * L.usplit);
-        P->coef16 = s; s += align256(sizeof(uint16_t) * 16 * L.csplit);
-        P->rhs32 = s; s += align256(sizeof(float) * 2 * L.csplit);
     }
     P->step_bytes = s - off;
 

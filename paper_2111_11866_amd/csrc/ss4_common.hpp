@@ -76,6 +76,25 @@ inline Layout make_layout(const int32_t n[4])
     return L;
 }
 
+// Index of the 16-byte mixed-precision record (8 BF16 coefficients divided by
+// the FP64 diagonal) of slot m in interior row r of colour `colour`; the FP32
+// scaled residual of the same cell uses the same index into a float array.
+__host__ __device__ __forceinline__ int64_t mrec(const Layout& L, int colour, int64_t r, int m)
+{
+    return (((int64_t)colour * L.nrow_int + r) * L.ntm + (m >> kTileShift)) * kTileSlots + (m & (kTileSlots - 1));
+}
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ uint32_t bf16_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
 // Index of field 0 of slot m in interior row r of colour `colour` in the tiled
 // coefficient block; field f is at +f*kTileSlots.
 __host__ __device__ __forceinline__ int64_t ctile(const Layout& L, int colour, int64_t r, int m)

@@ -19,7 +19,7 @@ struct WsPlan {
     // time step
     size_t ured0 = 0, ured1 = 0, ublack = 0, coef = 0, rhs = 0;
     // mixed precision (inside the step region)
-    size_t xf64 = 0, rf32 = 0, dred0 = 0, dred1 = 0, dblack = 0, coef16 = 0, rhs32 = 0;
+    size_t coef16 = 0, rf32 = 0, dred = 0, dblack = 0;
     // preparation
     size_t I0 = 0, ITH = 0, S0 = 0, S1 = 0;
     size_t step_bytes = 0, prep_bytes = 0, total = 0;
@@ -74,6 +74,8 @@ int run_solve(const WsPlan& P, const double* coef, const double* b, double* u,
 int run_sor_loop(const WsPlan& P, const subsurf4d_step_params& sp, void* ws, hipStream_t s,
                  subsurf4d_result* res);
 int run_unsplit(const WsPlan& P, double* u, void* ws, hipStream_t s);
+int launch_assembly(const WsPlan& P, double h, const double* G, const double* w, const subsurf4d_step_params& sp,
+                    void* coef16, void* ws, hipStream_t s);
 int run_copy_probe(const void* src, void* dst, size_t bytes, int reps, double* ms, hipStream_t s);
 
 // mixed precision (mixed.hip)
@@ -109,6 +111,7 @@ public:
         if (a_) (void)hipEventDestroy(a_);
         if (b_) (void)hipEventDestroy(b_);
     }
+    hipEvent_t end_event() const { return on_ ? b_ : nullptr; }
     void begin() { if (on_) (void)hipEventRecord(a_, s_); }
     void end() { if (on_) (void)hipEventRecord(b_, s_); }
     void collect()

@@ -24,6 +24,7 @@ struct AsmArgs {
     double* ured1;
     double* ublack;
     double* coef;     // tiled coefficient + rhs block, both colours
+    uint4* coef16;    // optional: normalised BF16 coefficient records (mixed precision)
     double* coef_nat; // interior x 8
     double* b_nat;    // interior
     double* part_a;
@@ -118,6 +119,14 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
 #pragma unroll
             for (int f = 0; f < 8; ++f) a.coef[ci + f * kTileSlots] = c[f];
             a.coef[ci + 8 * kTileSlots] = w0;
+            if (a.coef16) {
+                const double inv = 1.0 / D;
+                uint32_t h[8];
+#pragma unroll
+                for (int f = 0; f < 8; ++f) h[f] = bf16_bits((float)(c[f] * inv));
+                a.coef16[mrec(L, colour, irow, m)] =
+                    make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+            }
         } else {
             const int64_t qi = irow * L.n1 + (i - 1);
 #pragma unroll
@@ -733,6 +742,29 @@ int run_assemble_export(const Layout& L, double h, const double* G, const double
     return 0;
 }
 
+int launch_assembly(const WsPlan& P, double h, const double* G, const double* w, const subsurf4d_step_params& sp,
+                    void* coef16, void* ws, hipStream_t s)
+{
+    AsmArgs a{};
+    a.L = P.L;
+    a.th2 = sp.tau / (h * h);
+    a.eps2 = sp.eps * sp.eps;
+    a.inv_h = 1.0 / h;
+    a.G = G;
+    a.w = w;
+    a.ured0 = ws_ptr<double>(ws, P.ured0);
+    a.ured1 = ws_ptr<double>(ws, P.ured1);
+    a.ublack = ws_ptr<double>(ws, P.ublack);
+    a.coef = ws_ptr<double>(ws, P.coef);
+    a.coef16 = static_cast<uint4*>(coef16);
+    a.part_a = ws_ptr<double>(ws, P.part_a);
+    a.part_b = ws_ptr<double>(ws, P.part_b);
+    a.C = ws_ptr<Ctrl>(ws, P.ctrl);
+    k_assemble<kSplit><<<grid_for(P.L.npad), kBlock, 0, s>>>(a);
+    SS4_LAUNCHED("assemble");
+    return 0;
+}
+
 int run_step(const WsPlan& P, double h, const double* G, const subsurf4d_centre* centres, int nc,
              const int32_t* owner, double* u, const subsurf4d_step_params& sp, subsurf4d_result* res,
              void* ws, hipStream_t s)
@@ -743,27 +775,15 @@ int run_step(const WsPlan& P, double h, const double* G, const subsurf4d_centre*
     if (sp.precision == SUBSURF4D_MIXED) {
         rc = run_mixed_solve(P, h, G, u, sp, res, ws, s);
         if (rc < 0) return rc;
+        rc = run_unsplit(P, u, ws, s);
+        if (rc < 0) return rc;
     } else {
         double tol;
         int max_iter;
         effective_stop(sp, &tol, &max_iter);
         k_ctrl_init<<<1, 64, 0, s>>>(C, tol, max_iter);
-        AsmArgs a{};
-        a.L = L;
-        a.th2 = sp.tau / (h * h);
-        a.eps2 = sp.eps * sp.eps;
-        a.inv_h = 1.0 / h;
-        a.G = G;
-        a.w = u;
-        a.ured0 = ws_ptr<double>(ws, P.ured0);
-        a.ured1 = ws_ptr<double>(ws, P.ured1);
-        a.ublack = ws_ptr<double>(ws, P.ublack);
-        a.coef = ws_ptr<double>(ws, P.coef);
-        a.part_a = ws_ptr<double>(ws, P.part_a);
-        a.part_b = ws_ptr<double>(ws, P.part_b);
-        a.C = C;
-        k_assemble<kSplit><<<grid_for(L.npad), kBlock, 0, s>>>(a);
-        SS4_LAUNCHED("assemble");
+        rc = launch_assembly(P, h, G, u, sp, nullptr, ws, s);
+        if (rc < 0) return rc;
         rc = run_sor_loop(P, sp, ws, s, res);
         if (rc < 0) return rc;
         rc = run_unsplit(P, u, ws, s);
