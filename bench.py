@@ -100,6 +100,106 @@ def cpu_baseline(img, pp, sp, seconds):
                       f"iterations incl. the oracle's per-iteration residual, {dt:.1f} s"}
 
 
+def bench_batch(n_windows, steps, plain_sample, log_steps=False):
+    """Config 4: n_windows uneven windows (x,y,z in 24..64, t in 3..9), each a
+    job of `steps` time steps.  Batched mixed-precision form (all windows in
+    every launch, graph-replayed passes) against the plain per-job FP64 form
+    timed on the first `plain_sample` windows."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2111_11866_amd import binding as B
+    from paper_2111_11866_amd import serve as S
+
+    pp, plain, mixed = S.default_params()
+    t0 = time.perf_counter()
+    imgs = synth.windows_cfg4(n_windows)
+    cells = sum(im.cells for im in imgs)
+    log(f"[batch] generated {n_windows} windows ({cells / 1e9:.2f} G cells) in {time.perf_counter() - t0:.1f}s")
+    shared = S._Shared(n_windows)
+    t0 = time.perf_counter()
+    wins = [S.Window(jid=q, arrival=0.0, img=im) for q, im in enumerate(imgs)]
+    for w in wins:
+        S.admit_window(w, pp, 1.0, 0.0, mixed.ball_r, shared)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t0
+    jobs = [w.state for w in wins]
+    B.step_batched(jobs, mixed, shared.table)          # one untimed step (tuning, warm caches)
+    for w in wins:                                    # restart every job from its initial function
+        w.state.init(v=1.0, R=0.0, ball_r=mixed.ball_r)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    passes = []
+    for st in range(steps):
+        rc, res = B.step_batched(jobs, mixed, shared.table)
+        passes.append(max(r["outer"] for r in res))
+        if log_steps:
+            log(f"[batch] step {st}: max passes {passes[-1]}")
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    batched_u = [w.state.u.cpu().numpy() for w in wins[:plain_sample]]
+    # plain per-job FP64 on a sample (same jobs, same initial function)
+    for w in wins[plain_sample:]:
+        w.state = None
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    errs = []
+    for q in range(plain_sample):
+        im = imgs[q]
+        job = B.Job(im.n, im.image, im.centres, im.seeds, precision=B.FP64)
+        job.prepare(pp)
+        job.init(v=1.0, R=0.0, ball_r=plain.ball_r)
+        for _ in range(steps):
+            job.step(plain)
+        ref = job.u.cpu().numpy()
+        errs.append(float(np.abs(ref - batched_u[q]).max() / max(np.abs(ref).max(), 1e-300)))
+        del job
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    plain_per_job = t_plain / plain_sample
+    return {
+        "windows": n_windows, "cells": cells, "steps_per_job": steps,
+        "batched_jobs_per_s": n_windows / t_batch,
+        "batched_step_ms": t_batch * 1e3 / steps,
+        "batched_voxel_steps_per_s": cells * steps / t_batch,
+        "refinement_passes_per_step_max": passes,
+        "prepare_s_all_windows": t_prep,
+        "plain_fp64_jobs_per_s": 1.0 / plain_per_job,
+        "plain_sample_jobs": plain_sample,
+        "speedup_jobs_per_s": (n_windows / t_batch) * plain_per_job,
+        "max_rel_err_batched_vs_plain_fp64": max(errs),
+        "note": "prepare (thresholding, presmoothing, G, initial function) is timed separately for the "
+                "batched form and included in the plain per-job time",
+    }
+
+
+def bench_serving(rates, count, plain_seconds, log=None):
+    """Config 5: Poisson arrivals of lognormal-size windows; continuous batching
+    against first-come-first-served plain FP64 per-job solves."""
+    import torch
+
+    from paper_2111_11866_amd import serve as S
+
+    pp, plain, mixed = S.default_params()
+    out = {}
+    for rate in rates:
+        wins = S.make_windows(rate, count)
+        bs = S.BatchServer(pp, mixed, steps=20, hbm_budget=96 << 30).run(wins)
+        del wins
+        torch.cuda.empty_cache()
+        wins = S.make_windows(rate, count)
+        ps = S.PlainServer(pp, plain, steps=20).run(wins, max_seconds=plain_seconds)
+        del wins
+        torch.cuda.empty_cache()
+        out[str(rate)] = {"batched": bs, "plain_fp64": ps}
+        if log:
+            log(f"[serve] rate {rate}/s: batched {bs['jobs_per_s']:.1f} jobs/s p50 {bs['p50_latency_s']:.3f}s "
+                f"p99 {bs['p99_latency_s']:.3f}s | plain {ps['jobs_per_s']:.1f} jobs/s "
+                f"p50 {ps['p50_latency_s']:.3f}s p99 {ps['p99_latency_s']:.3f}s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +211,13 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=-1,
                     help="also time this many steps with the mixed-precision solve (-1: same as --steps)")
     ap.add_argument("--inner", type=int, default=20, help="FP32 sweeps per refinement pass (mixed)")
+    ap.add_argument("--windows", type=int, default=2048, help="batched workload size (0: skip)")
+    ap.add_argument("--window-steps", type=int, default=20)
+    ap.add_argument("--plain-sample", type=int, default=24)
+    ap.add_argument("--serving-rate", type=float, default=1000.0, help="0: skip the serving run")
+    ap.add_argument("--serving-jobs", type=int, default=400)
+    ap.add_argument("--serving-sweep", action="store_true",
+                    help="arrival rates 200..5000 jobs/s with 2000 jobs each (long)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -247,6 +354,17 @@ def main():
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(img, pp, sp, args.cpu_seconds)
         log(f"[bench] cpu baseline in {time.perf_counter() - t0:.1f}s")
+    del job
+    torch.cuda.empty_cache()
+    if args.windows > 0:
+        t0 = time.perf_counter()
+        out["batched_windows"] = bench_batch(args.windows, args.window_steps, args.plain_sample)
+        log(f"[bench] batched windows in {time.perf_counter() - t0:.1f}s: {out['batched_windows']}")
+        torch.cuda.empty_cache()
+    if args.serving_sweep:
+        out["serving"] = bench_serving([200, 500, 1000, 2000, 5000], 2000, 60.0, log=log)
+    elif args.serving_rate > 0:
+        out["serving"] = bench_serving([args.serving_rate], args.serving_jobs, 15.0, log=log)
     print(json.dumps(out), flush=True)
 
 

@@ -83,7 +83,8 @@ typedef struct {
     double smooth_tau;    /* presmoothing: implicit heat-step size (>= 0) */
     int32_t smooth_steps; /* number of implicit heat steps (>= 0) */
     int32_t smooth_max_iter; /* SOR iteration cap of each heat step */
-    double smooth_omega;  /* SOR relaxation of the heat steps, in (0,2) */
+    double smooth_omega;  /* SOR relaxation of the heat steps, in (0,2); <= 0: Young's optimum
+                             2/(1+sqrt(1-rho^2)), rho = 8a/(1+8a), a = smooth_tau/h^2 */
     double smooth_tol;    /* relative L2 residual tolerance of the heat steps */
     double image_scale;   /* I0 = image_scale * image[...] */
 } subsurf4d_prepare_params;
@@ -101,10 +102,14 @@ typedef struct {
     double ball_r;        /* ball radius of the local rescaling */
     double refine_tol;    /* MIXED: FP64 relative residual target of refinement */
     int32_t inner_sweeps; /* MIXED: FP32 red-black iterations per refinement pass */
-    int32_t fixed_iters;  /* > 0: run exactly this many iterations (tol ignored) */
+    int32_t fixed_iters;  /* > 0: run exactly this many iterations (tol ignored; FP64 only) */
     int32_t iter_hint;    /* expected iteration count (0 = unknown); only sizes launch chunks */
-    int32_t reserved;
+    int32_t flags;        /* SUBSURF4D_FLAG_* bits */
 } subsurf4d_step_params;
+
+/* subsurf4d_step_params.flags: launch the refinement passes of a batched step
+ * one by one instead of replaying a captured HIP graph (same results). */
+#define SUBSURF4D_FLAG_NO_GRAPH 1
 
 /* Outcome of a solve.  Iterations are full red-black iterations. */
 typedef struct {
@@ -120,6 +125,10 @@ typedef struct {
  * `n_centres` ball centres, in the given precision.  Host-only; 0 if the grid
  * is invalid.  One workspace serves every call on the grid (not concurrently). */
 size_t subsurf4d_workspace_bytes(const subsurf4d_grid* grid, int32_t n_centres, int32_t precision);
+
+/* Bytes of workspace that subsurf4d_prepare_g needs (<= subsurf4d_workspace_bytes;
+ * the same amount also serves subsurf4d_rescale).  Host-only; 0 if invalid. */
+size_t subsurf4d_prepare_workspace_bytes(const subsurf4d_grid* grid, int32_t n_centres);
 
 /*
  * Per-job preparation (Sec. 3.1 local thresholding and presmoothing,
@@ -137,7 +146,7 @@ size_t subsurf4d_workspace_bytes(const subsurf4d_grid* grid, int32_t n_centres, 
  *    gradients of the smoothed images; image values outside the interior are
  *    copies of the nearest interior value.
  * image (device): interior array of `image_dtype`.  centres (device):
- * n_centres entries (0 allowed).  Returns SUBSURF4D_NOT_CONVERGED if a heat
+ * n_centres entries (0 allowed).  workspace: >= subsurf4d_prepare_workspace_bytes.  Returns SUBSURF4D_NOT_CONVERGED if a heat
  * step hit smooth_max_iter (G is still written).
  */
 int subsurf4d_prepare_g(const subsurf4d_grid* grid, const void* image, int32_t image_dtype,
@@ -160,8 +169,8 @@ int subsurf4d_init_u(const subsurf4d_grid* grid, const subsurf4d_centre* seeds, 
  * Local rescaling (Sec. 3.2.2 remark): for each ball m, mu_m/xi_m = min/max of
  * u over the ball; every cell with owner == m becomes (u - mu_m)/(xi_m - mu_m)
  * unless xi_m - mu_m < 1e-12.  u (device, padded) is rescaled in place; ghosts
- * and cells without an owner are unchanged.  Needs the workspace for the
- * per-ball extrema.
+ * and cells without an owner are unchanged.  Needs a workspace (>=
+ * subsurf4d_prepare_workspace_bytes) for the per-ball extrema.
  */
 int subsurf4d_rescale(const subsurf4d_grid* grid, const subsurf4d_centre* centres,
                       int32_t n_centres, double ball_r, const int32_t* owner, double* u,
@@ -222,6 +231,47 @@ int subsurf4d_solve(const subsurf4d_grid* grid, const double* coef, const double
  * byte counters (a copy of known size).
  */
 int subsurf4d_copy_probe(const void* src, void* dst, size_t bytes, int32_t reps, double* ms, void* stream);
+
+/*
+ * Batched time step over many independent windows (the per-nucleus windows
+ * the paper cuts around cells, Sec. 4), in mixed precision.  Each job is one
+ * window with its own grid, G, u, owner map, centres and workspace; every job
+ * gets exactly what subsurf4d_step with precision SUBSURF4D_MIXED computes
+ * for it (assembly, FP64-refined FP32/BF16 red-black SOR to refine_tol, local
+ * rescaling), but all jobs advance together: each kernel launch processes the
+ * work items of every unfinished job, and the refinement pass (FP64
+ * residual, `inner_sweeps` red-black iterations, update) is captured once as
+ * a HIP graph and replayed until every job has met its stopping rule.  A job's
+ * result does not depend on the other jobs of the batch (per-job reductions in
+ * a fixed order).
+ */
+typedef struct {
+    subsurf4d_grid grid;
+    const double* G;                  /* device, 4 x padded, from subsurf4d_prepare_g */
+    double* u;                        /* device, padded; in u^{resc;n-1}, out the new level */
+    const int32_t* owner;             /* device, interior, from subsurf4d_prepare_g */
+    const subsurf4d_centre* centres;  /* device, n_centres entries */
+    int32_t n_centres;
+    int32_t reserved;
+    void* workspace;                  /* device, >= subsurf4d_batch_workspace_bytes, 256-byte aligned */
+    size_t workspace_bytes;
+} subsurf4d_batch_job;
+
+/* Bytes of per-job workspace of the batched step (host-only; 0 if invalid). */
+size_t subsurf4d_batch_workspace_bytes(const subsurf4d_grid* grid, int32_t n_centres);
+
+/* Bytes of the shared device table of a batch of n_jobs jobs (host-only). */
+size_t subsurf4d_batch_table_bytes(int32_t n_jobs);
+
+/*
+ * Advance every job by one time step.  jobs (host array of n_jobs), params
+ * (precision must be SUBSURF4D_MIXED; fixed_iters is ignored), results (host
+ * array of n_jobs, may be NULL), table (device, >= subsurf4d_batch_table_bytes).
+ * Synchronises `stream`.  Returns SUBSURF4D_NOT_CONVERGED if any job hit its
+ * cap, SUBSURF4D_ENONFINITE if any job failed (see each job's result).
+ */
+int subsurf4d_step_batched(const subsurf4d_batch_job* jobs, int32_t n_jobs, const subsurf4d_step_params* params,
+                           subsurf4d_result* results, void* table, size_t table_bytes, void* stream);
 
 /* Static text for a status code. */
 const char* subsurf4d_status_string(int status);

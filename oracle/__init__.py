@@ -116,7 +116,15 @@ def threshold(n, I0, centres, r, lam, owner):
 
 
 def lhe_step(n, J, h, tau_s, omega=1.5, tol=1e-13, max_iter=100000):
-    """One implicit zero-Neumann heat step (presmoothing, Sec. 3.1); interior arrays."""
+    """One implicit zero-Neumann heat step (presmoothing, Sec. 3.1); interior arrays.
+
+    omega <= 0 selects Young's optimal relaxation for a consistently ordered
+    matrix with Jacobi spectral radius rho: 2/(1+sqrt(1-rho^2)), here with the
+    interior radius rho = 8a/(1+8a), a = tau_s/h^2 (8 neighbours in 4D)."""
+    if omega <= 0.0:
+        a = tau_s / (h * h)
+        rho = 8.0 * a / (1.0 + 8.0 * a)
+        omega = 2.0 / (1.0 + np.sqrt(1.0 - rho * rho))
     J = np.ascontiguousarray(J, dtype=np.float64)
     out = np.empty_like(J)
     it = lib().oracle_lhe_step(_ptr(_dims(n)), float(h), float(tau_s), float(omega), float(tol),
@@ -202,7 +210,7 @@ class PrepareParams:
     ball_r: float = 8.0
     smooth_tau: float = 0.1
     smooth_steps: int = 1
-    smooth_omega: float = 1.5
+    smooth_omega: float = 0.0          # <= 0: Young's optimal omega for the heat system
     smooth_tol: float = 1e-13
     h: float = 1.0
 

@@ -27,6 +27,8 @@ EXPORTED = (
     "subsurf4d_workspace_bytes", "subsurf4d_prepare_g", "subsurf4d_init_u", "subsurf4d_rescale",
     "subsurf4d_assemble", "subsurf4d_step", "subsurf4d_solve", "subsurf4d_status_string",
     "subsurf4d_last_error", "subsurf4d_version", "subsurf4d_timing", "subsurf4d_copy_probe",
+    "subsurf4d_batch_workspace_bytes", "subsurf4d_batch_table_bytes", "subsurf4d_step_batched",
+    "subsurf4d_prepare_workspace_bytes",
 )
 
 
@@ -47,7 +49,16 @@ class StepParamsC(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("rescale", ctypes.c_int32), ("precision", ctypes.c_int32), ("ball_r", ctypes.c_double),
                 ("refine_tol", ctypes.c_double), ("inner_sweeps", ctypes.c_int32),
-                ("fixed_iters", ctypes.c_int32), ("iter_hint", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fixed_iters", ctypes.c_int32), ("iter_hint", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+FLAG_NO_GRAPH = 1
+
+
+class BatchJobC(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("G", ctypes.c_void_p), ("u", ctypes.c_void_p), ("owner", ctypes.c_void_p),
+                ("centres", ctypes.c_void_p), ("n_centres", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 
 class Result(ctypes.Structure):
@@ -70,7 +81,7 @@ class PrepareParams:
     smooth_tau: float = 0.1
     smooth_steps: int = 1
     smooth_max_iter: int = 10000
-    smooth_omega: float = 1.5
+    smooth_omega: float = 0.0          # <= 0: optimal omega for the heat system
     smooth_tol: float = 1e-13
     image_scale: float = 1.0
 
@@ -95,11 +106,12 @@ class StepParams:
     inner_sweeps: int = 8
     fixed_iters: int = 0
     iter_hint: int = 0
+    flags: int = 0
 
     def c(self) -> StepParamsC:
         return StepParamsC(self.eps, self.tau, self.omega, self.tol, self.max_iter, self.check_every,
                            int(bool(self.rescale)), self.precision, self.ball_r, self.refine_tol,
-                           self.inner_sweeps, self.fixed_iters, self.iter_hint, 0)
+                           self.inner_sweeps, self.fixed_iters, self.iter_hint, self.flags)
 
 
 class Subsurf4dError(RuntimeError):
@@ -137,6 +149,14 @@ def lib():
         L.subsurf4d_timing.argtypes = [I, P, P, P, P]
         L.subsurf4d_timing.restype = None
         L.subsurf4d_copy_probe.argtypes = [P, P, SZ, I, P, P]
+        L.subsurf4d_batch_workspace_bytes.argtypes = [ctypes.POINTER(Grid), I]
+        L.subsurf4d_batch_workspace_bytes.restype = SZ
+        L.subsurf4d_prepare_workspace_bytes.argtypes = [ctypes.POINTER(Grid), I]
+        L.subsurf4d_prepare_workspace_bytes.restype = SZ
+        L.subsurf4d_batch_table_bytes.argtypes = [I]
+        L.subsurf4d_batch_table_bytes.restype = SZ
+        L.subsurf4d_step_batched.argtypes = [ctypes.POINTER(BatchJobC), I, ctypes.POINTER(StepParamsC),
+                                             ctypes.POINTER(Result), P, SZ, P]
         _lib = L
     return _lib
 
@@ -256,6 +276,31 @@ def copy_probe(src, dst, reps=10, stream=None) -> float:
     return ms.value
 
 
+def prepare_workspace_bytes(n, n_centres=0) -> int:
+    return int(lib().subsurf4d_prepare_workspace_bytes(ctypes.byref(grid(n)), int(n_centres)))
+
+
+def batch_workspace_bytes(n, n_centres=0, h=1.0) -> int:
+    return int(lib().subsurf4d_batch_workspace_bytes(ctypes.byref(grid(n, h)), int(n_centres)))
+
+
+def batch_table_bytes(n_jobs) -> int:
+    return int(lib().subsurf4d_batch_table_bytes(int(n_jobs)))
+
+
+def step_batched(jobs, params: StepParams, table, stream=None):
+    """jobs: sequence of objects with n, h, G, u, owner, centres, nc, bws (batch workspace).
+    Returns (status, list of per-job result dicts)."""
+    arr = (BatchJobC * len(jobs))()
+    for q, j in enumerate(jobs):
+        arr[q] = BatchJobC(grid(j.n, j.h), _p(j.G), _p(j.u), _p(j.owner), _p(j.centres), int(j.nc), 0,
+                           _p(j.bws), j.bws.numel())
+    res = (Result * len(jobs))()
+    rc = _check(lib().subsurf4d_step_batched(arr, len(jobs), ctypes.byref(params.c()), res, _p(table),
+                                              table.numel(), _stream(stream)))
+    return rc, [r.as_dict() for r in res]
+
+
 def version() -> str:
     return lib().subsurf4d_version().decode()
 
@@ -265,7 +310,8 @@ class Job:
     workspace), with the pipeline of the implementation overview (Sec. 3.5):
     prepare -> initial function -> rescale -> steps.  Memory comes from torch."""
 
-    def __init__(self, n, image_np, centres, seeds, h=1.0, precision=FP64, device="cuda"):
+    def __init__(self, n, image_np, centres, seeds, h=1.0, precision=FP64, device="cuda", batch=False,
+                 shared_ws=None):
         import torch
 
         self.n, self.h, self.device = tuple(int(v) for v in n), float(h), device
@@ -275,7 +321,15 @@ class Job:
         self.G = torch.empty((4,) + padded_shape(self.n), dtype=torch.float64, device=device)
         self.owner = torch.empty(interior_shape(self.n), dtype=torch.int32, device=device)
         self.u = torch.empty(padded_shape(self.n), dtype=torch.float64, device=device)
-        self.ws = alloc_workspace(self.n, self.nc, precision, device)
+        # full single-job workspace, or a caller-shared one (e.g. one preparation
+        # workspace reused by many batched windows)
+        self.ws = shared_ws if shared_ws is not None else alloc_workspace(self.n, self.nc, precision, device)
+        self.bws = None
+        if batch:
+            import torch
+
+            self.bws = torch.empty(batch_workspace_bytes(self.n, self.nc, self.h), dtype=torch.uint8,
+                                   device=device)
         self.last_iters = 0
 
     def prepare(self, pp: PrepareParams):

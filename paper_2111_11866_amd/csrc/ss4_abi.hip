@@ -116,6 +116,7 @@ static_assert(sizeof(subsurf4d_centre) == 16, "centre layout");
 static_assert(sizeof(subsurf4d_prepare_params) == 80, "prepare params layout");
 static_assert(sizeof(subsurf4d_step_params) == 80, "step params layout");
 static_assert(sizeof(subsurf4d_result) == 32, "result layout");
+static_assert(sizeof(subsurf4d_batch_job) == 80, "batch job layout");
 
 namespace {
 
@@ -134,10 +135,11 @@ int check_grid(const subsurf4d_grid* g)
     return 0;
 }
 
-int check_ws(const WsPlan& P, void* ws, size_t bytes)
+int check_ws(const WsPlan& P, void* ws, size_t bytes, size_t need = 0)
 {
     if (!ws) return fail(SUBSURF4D_EINVAL, "workspace is NULL");
-    if (bytes < P.total) return fail(SUBSURF4D_EWORKSPACE, "workspace too small (see subsurf4d_workspace_bytes)");
+    if (need == 0) need = P.total;
+    if (bytes < need) return fail(SUBSURF4D_EWORKSPACE, "workspace too small (see subsurf4d_workspace_bytes)");
     if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(SUBSURF4D_EINVAL, "workspace must be 256-byte aligned");
     return 0;
 }
@@ -185,6 +187,20 @@ size_t subsurf4d_workspace_bytes(const subsurf4d_grid* grid, int32_t n_centres, 
     }
 }
 
+size_t subsurf4d_prepare_workspace_bytes(const subsurf4d_grid* grid, int32_t n_centres)
+{
+    try {
+        if (!grid || n_centres < 0) return 0;
+        for (int d = 0; d < 4; ++d)
+            if (grid->n[d] < 1 || grid->n[d] > (1 << 20)) return 0;
+        WsPlan P;
+        if (!plan_workspace(grid->n, n_centres, SUBSURF4D_FP64, &P)) return 0;
+        return P.big + P.prep_bytes;
+    } catch (...) {
+        return 0;
+    }
+}
+
 int subsurf4d_prepare_g(const subsurf4d_grid* grid, const void* image, int32_t image_dtype,
                         const subsurf4d_centre* centres, int32_t n_centres,
                         const subsurf4d_prepare_params* params, double* G, int32_t* owner, void* workspace,
@@ -202,13 +218,13 @@ int subsurf4d_prepare_g(const subsurf4d_grid* grid, const void* image, int32_t i
     if (!(p.lambda >= 0.0 && p.lambda <= 1.0)) return fail(SUBSURF4D_EINVAL, "lambda must be in [0,1]");
     if (!(p.ball_r >= 0.0 && p.ball_r <= 1e6)) return fail(SUBSURF4D_EINVAL, "ball_r out of range");
     if (!(p.smooth_tau >= 0.0) || p.smooth_steps < 0) return fail(SUBSURF4D_EINVAL, "bad smoothing parameters");
-    if (p.smooth_steps > 0 && (!(p.smooth_omega > 0.0 && p.smooth_omega < 2.0) || p.smooth_max_iter < 1 ||
+    if (p.smooth_steps > 0 && (!(p.smooth_omega < 2.0) || p.smooth_max_iter < 1 ||
                                !(p.smooth_tol >= 0.0)))
         return fail(SUBSURF4D_EINVAL, "bad smoothing solver parameters");
     if (!std::isfinite(p.image_scale)) return fail(SUBSURF4D_EINVAL, "image_scale must be finite");
     WsPlan P;
     if (!plan_workspace(grid->n, n_centres, SUBSURF4D_FP64, &P)) return fail(SUBSURF4D_ESHAPE, "grid too large");
-    if (int rc = check_ws(P, workspace, workspace_bytes)) return rc;
+    if (int rc = check_ws(P, workspace, workspace_bytes, P.big + P.prep_bytes)) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int rc = run_prepare(P, grid->h, image, image_dtype, centres, n_centres, p, G, owner, workspace, s);
     if (rc < 0) return rc;
@@ -243,7 +259,7 @@ int subsurf4d_rescale(const subsurf4d_grid* grid, const subsurf4d_centre* centre
     if (!(ball_r >= 0.0 && ball_r <= 1e6)) return fail(SUBSURF4D_EINVAL, "ball_r out of range");
     WsPlan P;
     if (!plan_workspace(grid->n, n_centres, SUBSURF4D_FP64, &P)) return fail(SUBSURF4D_ESHAPE, "grid too large");
-    if (int rc = check_ws(P, workspace, workspace_bytes)) return rc;
+    if (int rc = check_ws(P, workspace, workspace_bytes, P.big)) return rc;
     return run_rescale(P, centres, n_centres, ball_r, owner, u, workspace, static_cast<hipStream_t>(stream));
     SS4_GUARD_END
 }
@@ -309,6 +325,43 @@ int subsurf4d_copy_probe(const void* src, void* dst, size_t bytes, int32_t reps,
     if (reinterpret_cast<uintptr_t>(src) % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0)
         return fail(SUBSURF4D_EINVAL, "buffers must be 16-byte aligned");
     return run_copy_probe(src, dst, bytes, reps, ms, static_cast<hipStream_t>(stream));
+    SS4_GUARD_END
+}
+
+size_t subsurf4d_batch_workspace_bytes(const subsurf4d_grid* grid, int32_t n_centres)
+{
+    try {
+        if (!grid || n_centres < 0) return 0;
+        return batch_job_bytes(grid->n, n_centres);
+    } catch (...) {
+        return 0;
+    }
+}
+
+size_t subsurf4d_batch_table_bytes(int32_t n_jobs)
+{
+    return n_jobs > 0 ? batch_table_bytes(n_jobs) : 0;
+}
+
+int subsurf4d_step_batched(const subsurf4d_batch_job* jobs, int32_t n_jobs, const subsurf4d_step_params* params,
+                           subsurf4d_result* results, void* table, size_t table_bytes, void* stream)
+{
+    SS4_GUARD_BEGIN
+    g_error.clear();
+    if (!jobs || n_jobs < 1 || !table) return fail(SUBSURF4D_EINVAL, "bad batch arguments");
+    if (int rc = check_step_params(params)) return rc;
+    if (params->precision != SUBSURF4D_MIXED) return fail(SUBSURF4D_EINVAL, "the batched step is mixed precision");
+    if (reinterpret_cast<uintptr_t>(table) % 256 != 0) return fail(SUBSURF4D_EINVAL, "table must be 256-byte aligned");
+    for (int q = 0; q < n_jobs; ++q) {
+        const subsurf4d_batch_job& j = jobs[q];
+        if (int rc = check_grid(&j.grid)) return rc;
+        if (!j.G || !j.u || !j.workspace) return fail(SUBSURF4D_EINVAL, "batch job with a NULL pointer");
+        if (reinterpret_cast<uintptr_t>(j.workspace) % 256 != 0)
+            return fail(SUBSURF4D_EINVAL, "job workspace must be 256-byte aligned");
+        if (params->rescale && (j.n_centres < 0 || (j.n_centres > 0 && (!j.centres || !j.owner))))
+            return fail(SUBSURF4D_EINVAL, "rescale needs centres and owner");
+    }
+    return run_batch_step(jobs, n_jobs, *params, results, table, table_bytes, static_cast<hipStream_t>(stream));
     SS4_GUARD_END
 }
 

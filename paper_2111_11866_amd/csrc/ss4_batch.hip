@@ -1,0 +1,832 @@
+// Batched time step over many independent windows (one job per window), in
+// mixed precision: FP32 red-black sweeps on BF16 scaled coefficients inside
+// an FP64 iterative refinement (as ss4_mixed.hip), for every job at once.
+//
+// Layout per job ("flat"): for each colour, the cells of interior row r and
+// slot m = (i-1)>>1 are numbered q = r*half + m (half = ceil(N1/2)); a slot is
+// a cell of that colour when m < ceil/floor(N1/2) for the row's parity.  The
+// colour-split iterate x (FP64) and correction d (FP32) keep every padded row
+// with row stride half+2 (slot m at 1+m, ghosts at 0 and N1>>1 + 1).
+// Coefficients are tiled by 128 consecutive q (9 FP64 fields per tile), the
+// BF16 records and r/D are dense in q.  Small windows waste no lanes on row
+// padding: 256 consecutive q of one colour form a work item.
+//
+// Every launch walks a global list of work items of all unfinished jobs with
+// a resident-size grid.  Each job reduces its own per-item partial sums in a
+// fixed order when its last item arrives, so a job's result does not depend
+// on which other jobs share the launch.
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "ss4_internal.hpp"
+
+namespace ss4 {
+
+struct BJob {
+    int n1, n2, n3, n4, p1, p2, p3, p4;
+    int half, rsu, nc, pad0;
+    int64_t nrow_int, nrow_pad, npad, nint;
+    int64_t ncq;          // flat cells of one colour (incl. inactive slots)
+    int64_t ntq;          // 128-tiles of one colour
+    int64_t nip, nit;     // items over padded cells / over one colour
+    double th2, eps2, inv_h;
+    const double* G;
+    double* u;
+    const int32_t* owner;
+    const subsurf4d_centre* centres;
+    double* xr;
+    double* xb;
+    double* coef;
+    uint4* c16;
+    float* rf;
+    float* dr;
+    float* db;
+    double* part_a;       // per-item partials (>= max(nip, 2*nit))
+    double* part_b;
+    double* ball;         // mu, xi per centre
+    Ctrl* C;
+};
+
+struct BTable {
+    BJob* jobs;
+    Ctrl* out;            // gathered per-job control blocks (n_jobs)
+    int64_t* asm_start;   // prefix of nip
+    int64_t* col_start;   // prefix of nit
+    int64_t* both_start;  // prefix of 2*nit
+    int64_t* ball_start;  // prefix of nc
+    int* active;          // jobs not finished
+    int* pass;            // refinement pass counter (device, for graph replay)
+    int n_jobs;
+    int max_outer;
+    float omega;
+    int pad;
+};
+
+namespace {
+
+constexpr int kItem = 256;
+
+__device__ __forceinline__ int find_job(const int64_t* start, int n, int64_t w)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Contiguous range of work items of this block (one binary search per block,
+// then a linear walk through the job prefix array): consecutive items of a job
+// stay on one block, which keeps its neighbour rows warm in cache.
+struct ItemWalk {
+    int64_t w, end;
+    int jb;
+    const int64_t* start;
+    __device__ ItemWalk(const int64_t* st, int n_jobs) : start(st)
+    {
+        const int64_t total = st[n_jobs];
+        const int64_t per = (total + gridDim.x - 1) / gridDim.x;
+        w = (int64_t)blockIdx.x * per;
+        end = w + per < total ? w + per : total;
+        jb = w < end ? find_job(st, n_jobs, w) : 0;
+    }
+    __device__ bool next()
+    {
+        if (w >= end) return false;
+        while (start[jb + 1] <= w) ++jb;
+        return true;
+    }
+};
+
+__device__ __forceinline__ int64_t bprow(const BJob& J, int j, int k, int l)
+{
+    return ((int64_t)l * J.p3 + k) * J.p2 + j;
+}
+
+__device__ __forceinline__ int64_t bctile(const BJob& J, int colour, int64_t q)
+{
+    return (((int64_t)colour * J.ntq + (q >> kTileShift)) * kTileFields) * kTileSlots + (q & (kTileSlots - 1));
+}
+
+// decode flat q of colour `colour`: returns false for an inactive slot
+__device__ __forceinline__ bool bdecode(const BJob& J, int colour, int64_t q, int64_t& r, int& m, int& j, int& k,
+                                        int& l, int& par)
+{
+    if (q >= J.ncq) return false;
+    const uint32_t q32 = (uint32_t)q;                    // per-job sizes stay below 2^31 cells
+    const uint32_t r32 = q32 / (uint32_t)J.half;
+    m = (int)(q32 - r32 * (uint32_t)J.half);
+    const uint32_t r2 = r32 / (uint32_t)J.n2;
+    j = (int)(r32 - r2 * (uint32_t)J.n2) + 1;
+    const uint32_t r3 = r2 / (uint32_t)J.n3;
+    k = (int)(r2 - r3 * (uint32_t)J.n3) + 1;
+    l = (int)r3 + 1;
+    r = r32;
+    par = (colour + j + k + l) & 1;
+    const int cnt = par ? (J.n1 + 1) >> 1 : J.n1 >> 1;
+    return m < cnt;
+}
+
+__global__ void kb_init(BTable T, double tol, int max_outer)
+{
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < T.n_jobs; j += gridDim.x * blockDim.x) {
+        Ctrl* C = T.jobs[j].C;
+        for (int a = 0; a < 4; ++a) C->arrive[a] = 0;
+        C->done = 0;
+        C->iterations = 0;
+        C->status = SUBSURF4D_OK;
+        C->final_red = 0;
+        C->bn = 0.0;
+        C->rel_res = 0.0;
+        C->tol = tol;
+        C->max_iter = max_outer;
+        C->outer = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *T.active = T.n_jobs;
+        *T.pass = 0;
+    }
+}
+
+// Assembly of every job (one thread per padded cell), writing the flat layout.
+__global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
+{
+    __shared__ double lds[4];
+    for (ItemWalk it(T.asm_start, T.n_jobs); it.next(); ++it.w) {
+        const int jb = it.jb;
+        const BJob& J = T.jobs[jb];
+        const int64_t item = it.w - T.asm_start[jb];
+        const int64_t p = item * kItem + threadIdx.x;
+        double acc_b = 0.0, acc_r = 0.0;
+        if (p < J.npad) {
+            const int i = (int)(p % J.p1);
+            const int64_t prow = p / J.p1;
+            const int j = (int)(prow % J.p2);
+            const int64_t t2 = prow / J.p2;
+            const int k = (int)(t2 % J.p3);
+            const int l = (int)(t2 / J.p3);
+            const int colour = (i + j + k + l) & 1;
+            const int m = (i - 1) >> 1;
+            const double w0 = J.u[p];
+            const int64_t us = prow * J.rsu + 1 + m;
+            if (colour == 0) J.xr[us] = w0;
+            else J.xb[us] = w0;
+            const bool inside = i >= 1 && i <= J.n1 && j >= 1 && j <= J.n2 && k >= 1 && k <= J.n3 && l >= 1 && l <= J.n4;
+            if (inside) {
+                const int64_t sd[4] = {1, J.p1, (int64_t)J.p1 * J.p2, (int64_t)J.p1 * J.p2 * J.p3};
+                const int idx[4] = {i, j, k, l};
+                const int nn[4] = {J.n1, J.n2, J.n3, J.n4};
+                double wm[4], wp[4], q[8];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) { wm[d] = J.u[p - sd[d]]; wp[d] = J.u[p + sd[d]]; }
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const double gnm = (w0 - wm[d]) * J.inv_h;
+                    const double gnp = (wp[d] - w0) * J.inv_h;
+                    double qm = gnm * gnm, qp = gnp * gnp;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        if (t == d) continue;
+                        const double wpt = J.u[p + sd[t]], wmt = J.u[p - sd[t]];
+                        const double dm_pt = J.u[p - sd[d] + sd[t]], dm_mt = J.u[p - sd[d] - sd[t]];
+                        const double dp_pt = J.u[p + sd[d] + sd[t]], dp_mt = J.u[p + sd[d] - sd[t]];
+                        const double tm = ((dm_pt + wpt) - (dm_mt + wmt)) * (0.25 * J.inv_h);
+                        const double tp = ((wpt + dp_pt) - (wmt + dp_mt)) * (0.25 * J.inv_h);
+                        qm += tm * tm;
+                        qp += tp * tp;
+                    }
+                    q[2 * d] = qm;
+                    q[2 * d + 1] = qp;
+                }
+                double qs = 0.0;
+#pragma unroll
+                for (int f = 0; f < 8; ++f) qs += q[f];
+                const double scale = J.th2 * sqrt(J.eps2 + qs / 8.0);
+                double c[8];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    c[2 * d] = scale * J.G[(int64_t)d * J.npad + p - sd[d]] / sqrt(J.eps2 + q[2 * d]);
+                    c[2 * d + 1] = scale * J.G[(int64_t)d * J.npad + p] / sqrt(J.eps2 + q[2 * d + 1]);
+                }
+                double D = 1.0, bfull = w0, off = 0.0;
+#pragma unroll
+                for (int f = 0; f < 8; ++f) D += c[f];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    off += c[2 * d] * wm[d] + c[2 * d + 1] * wp[d];
+                    if (idx[d] == 1) bfull += c[2 * d] * wm[d];
+                    if (idx[d] == nn[d]) bfull += c[2 * d + 1] * wp[d];
+                }
+                const double r0 = (w0 + off) - D * w0;
+                acc_b = bfull * bfull;
+                acc_r = r0 * r0;
+                const int64_t irow = ((int64_t)(l - 1) * J.n3 + (k - 1)) * J.n2 + (j - 1);
+                const int64_t qf = irow * J.half + m;
+                const int64_t ci = bctile(J, colour, qf);
+#pragma unroll
+                for (int f = 0; f < 8; ++f) J.coef[ci + f * kTileSlots] = c[f];
+                J.coef[ci + 8 * kTileSlots] = w0;
+                const double inv = 1.0 / D;
+                uint32_t hb[8];
+#pragma unroll
+                for (int f = 0; f < 8; ++f) hb[f] = bf16_bits((float)(c[f] * inv));
+                J.c16[(int64_t)colour * J.ntq * kTileSlots + qf] =
+                    make_uint4(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16), hb[4] | (hb[5] << 16), hb[6] | (hb[7] << 16));
+            }
+        }
+        const double bb = block_sum(acc_b, lds);
+        const double rr = block_sum(acc_r, lds);
+        if (threadIdx.x == 0) { J.part_a[item] = bb; J.part_b[item] = rr; }
+    }
+}
+
+// Per-job fixed-order reduction of the assembly partials (one block per job):
+// ||b||_2 and the residual of iterate 0.
+__global__ __launch_bounds__(kBlock) void kb_assemble_decide(BTable T)
+{
+    __shared__ double lds[4];
+    for (int jb = blockIdx.x; jb < T.n_jobs; jb += gridDim.x) {
+        const BJob& J = T.jobs[jb];
+        const double B2 = sum_partials(J.part_a, (int)J.nip, lds);
+        const double R2 = sum_partials(J.part_b, (int)J.nip, lds);
+        if (threadIdx.x == 0) {
+            Ctrl* C = J.C;
+            C->bn = sqrt(B2);
+            const double R = sqrt(R2);
+            C->rel_res = C->bn > 0.0 ? R / C->bn : R;
+            if (!(R2 < INFINITY) || !(B2 < INFINITY)) { C->status = SUBSURF4D_ENONFINITE; C->done = 1; }
+            else if (R <= C->tol * C->bn) C->done = 1;
+            if (C->done) atomicSub(T.active, 1);
+        }
+        __syncthreads();
+    }
+}
+
+// FP64 residual of x (both colours) for unfinished jobs; r/D to FP32; the
+// last item of each job applies its stopping rule.
+__global__ __launch_bounds__(kBlock) void kb_residual(BTable T)
+{
+    __shared__ double lds[4];
+    for (ItemWalk it(T.both_start, T.n_jobs); it.next(); ++it.w) {
+        const int jb = it.jb;
+        const BJob& J = T.jobs[jb];
+        if (J.C->done) continue;
+        const int64_t item = it.w - T.both_start[jb];
+        const int colour = item >= J.nit ? 1 : 0;
+        const int64_t q = (item - colour * J.nit) * kItem + threadIdx.x;
+        double acc = 0.0;
+        int64_t r;
+        int m, j, k, l, par;
+        if (bdecode(J, colour, q, r, m, j, k, l, par)) {
+            const int64_t sy = J.rsu, sz = (int64_t)J.p2 * J.rsu, st = (int64_t)J.p2 * J.p3 * J.rsu;
+            const int64_t ui = bprow(J, j, k, l) * J.rsu + 1 + m;
+            const double* own = colour ? J.xb : J.xr;
+            const double* oth = colour ? J.xr : J.xb;
+            const double* cf = J.coef + bctile(J, colour, q);
+            const double c0 = cf[0], c1 = cf[kTileSlots], c2 = cf[2 * kTileSlots], c3 = cf[3 * kTileSlots];
+            const double c4 = cf[4 * kTileSlots], c5 = cf[5 * kTileSlots], c6 = cf[6 * kTileSlots];
+            const double c7 = cf[7 * kTileSlots];
+            double s = cf[8 * kTileSlots];
+            s += c0 * oth[ui - par] + c1 * oth[ui + 1 - par];
+            s += c2 * oth[ui - sy] + c3 * oth[ui + sy];
+            s += c4 * oth[ui - sz] + c5 * oth[ui + sz];
+            s += c6 * oth[ui - st] + c7 * oth[ui + st];
+            const double D = ((((((((1.0 + c0) + c1) + c2) + c3) + c4) + c5) + c6) + c7);
+            const double res = s - D * own[ui];
+            acc = res * res;
+            J.rf[(int64_t)colour * J.ntq * kTileSlots + q] = (float)(res / D);
+        }
+        const double bs = block_sum(acc, lds);
+        if (threadIdx.x == 0) J.part_a[item] = bs;
+    }
+}
+
+// Per-job fixed-order reduction of the residual partials and the refinement
+// stopping rule (one block per unfinished job).
+__global__ __launch_bounds__(kBlock) void kb_residual_decide(BTable T)
+{
+    __shared__ double lds[4];
+    const int pass = *T.pass;
+    for (int jb = blockIdx.x; jb < T.n_jobs; jb += gridDim.x) {
+        const BJob& J = T.jobs[jb];
+        if (J.C->done) continue;
+        const double R2 = sum_partials(J.part_a, (int)(2 * J.nit), lds);
+        if (threadIdx.x == 0) {
+            Ctrl* C = J.C;
+            const double R = sqrt(R2);
+            C->rel_res = C->bn > 0.0 ? R / C->bn : R;
+            C->outer = pass;
+            if (!(R2 < INFINITY)) { C->status = SUBSURF4D_ENONFINITE; C->done = 1; }
+            else if (R <= C->tol * C->bn) { C->status = SUBSURF4D_OK; C->done = 1; }
+            else if (pass >= T.max_outer) { C->status = SUBSURF4D_NOT_CONVERGED; C->done = 1; }
+            if (C->done) atomicSub(T.active, 1);
+        }
+        __syncthreads();
+    }
+}
+
+// FP32 half-sweep of colour COLOR on the scaled correction system.
+template <int COLOR>
+__global__ __launch_bounds__(kBlock) void kb_sweep(BTable T)
+{
+    const float om = T.omega, om1 = 1.0f - T.omega;
+    for (ItemWalk it(T.col_start, T.n_jobs); it.next(); ++it.w) {
+        const int jb = it.jb;
+        const BJob& J = T.jobs[jb];
+        if (J.C->done) continue;
+        const int64_t q = (it.w - T.col_start[jb]) * kItem + threadIdx.x;
+        int64_t r;
+        int m, j, k, l, par;
+        if (!bdecode(J, COLOR, q, r, m, j, k, l, par)) continue;
+        const int64_t sy = J.rsu, sz = (int64_t)J.p2 * J.rsu, st = (int64_t)J.p2 * J.p3 * J.rsu;
+        const int64_t ui = bprow(J, j, k, l) * J.rsu + 1 + m;
+        float* own = COLOR ? J.db : J.dr;
+        const float* oth = COLOR ? J.dr : J.db;
+        const int64_t qi = (int64_t)COLOR * J.ntq * kTileSlots + q;
+        const uint4 cw = J.c16[qi];
+        float s = J.rf[qi];
+        s += bf16_lo(cw.x) * oth[ui - par] + bf16_hi(cw.x) * oth[ui + 1 - par];
+        s += bf16_lo(cw.y) * oth[ui - sy] + bf16_hi(cw.y) * oth[ui + sy];
+        s += bf16_lo(cw.z) * oth[ui - sz] + bf16_hi(cw.z) * oth[ui + sz];
+        s += bf16_lo(cw.w) * oth[ui - st] + bf16_hi(cw.w) * oth[ui + st];
+        own[ui] = om * s + om1 * own[ui];
+    }
+}
+
+// x += d, d = 0 for unfinished jobs; the last block advances the pass counter.
+__global__ __launch_bounds__(kBlock) void kb_update(BTable T)
+{
+    for (ItemWalk it(T.both_start, T.n_jobs); it.next(); ++it.w) {
+        const int jb = it.jb;
+        const BJob& J = T.jobs[jb];
+        if (J.C->done) continue;
+        const int64_t item = it.w - T.both_start[jb];
+        const int colour = item >= J.nit ? 1 : 0;
+        const int64_t q = (item - colour * J.nit) * kItem + threadIdx.x;
+        int64_t r;
+        int m, j, k, l, par;
+        if (!bdecode(J, colour, q, r, m, j, k, l, par)) continue;
+        const int64_t ui = bprow(J, j, k, l) * J.rsu + 1 + m;
+        double* x = colour ? J.xb : J.xr;
+        float* d = colour ? J.db : J.dr;
+        x[ui] += (double)d[ui];
+        d[ui] = 0.0f;
+    }
+}
+
+__global__ void kb_gather(BTable T)
+{
+    for (int jb = blockIdx.x * blockDim.x + threadIdx.x; jb < T.n_jobs; jb += gridDim.x * blockDim.x)
+        T.out[jb] = *T.jobs[jb].C;
+}
+
+__global__ void kb_next_pass(BTable T)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *T.pass += 1;
+}
+
+// zero both corrections of every job (ghost slots included)
+__global__ void kb_zero_d(BTable T)
+{
+    for (int jb = blockIdx.y; jb < T.n_jobs; jb += gridDim.y) {
+        const BJob& J = T.jobs[jb];
+        const int64_t n = J.nrow_pad * J.rsu;
+        for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+            J.dr[q] = 0.0f;
+            J.db[q] = 0.0f;
+        }
+    }
+}
+
+// x -> interior of the padded u, every job
+__global__ __launch_bounds__(kBlock) void kb_unsplit(BTable T)
+{
+    for (ItemWalk it(T.both_start, T.n_jobs); it.next(); ++it.w) {
+        const int jb = it.jb;
+        const BJob& J = T.jobs[jb];
+        const int64_t item = it.w - T.both_start[jb];
+        const int colour = item >= J.nit ? 1 : 0;
+        const int64_t q = (item - colour * J.nit) * kItem + threadIdx.x;
+        int64_t r;
+        int m, j, k, l, par;
+        if (!bdecode(J, colour, q, r, m, j, k, l, par)) continue;
+        const int i = 2 * m + 2 - (par ? 1 : 0);
+        const int64_t prow = bprow(J, j, k, l);
+        J.u[prow * J.p1 + i] = (colour ? J.xb : J.xr)[prow * J.rsu + 1 + m];
+    }
+}
+
+// local rescaling of every job: one block per ball (global ball list)
+__device__ __forceinline__ bool bball(const BJob& J, const subsurf4d_centre& c, double r, int& lo0, int& lo1, int& lo2,
+                                      int& w0, int& w1, int64_t& count)
+{
+    if (c.frame < 0 || c.frame >= J.n4) return false;
+    const double cc[3] = {(double)c.x, (double)c.y, (double)c.z};
+    const int n[3] = {J.n1, J.n2, J.n3};
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        int v = (int)floor(cc[a] - r);
+        lo[a] = v < 1 ? 1 : (v > n[a] ? n[a] : v);
+        v = (int)ceil(cc[a] + r) + 2;
+        hi[a] = v < 1 ? 1 : (v > n[a] ? n[a] : v);
+    }
+    lo0 = lo[0]; lo1 = lo[1]; lo2 = lo[2];
+    w0 = hi[0] - lo[0] + 1;
+    w1 = hi[1] - lo[1] + 1;
+    count = (int64_t)w0 * w1 * (hi[2] - lo[2] + 1);
+    return true;
+}
+
+template <int PHASE>
+__global__ __launch_bounds__(kBlock) void kb_rescale(BTable T, double r)
+{
+    __shared__ double s_lo[4], s_hi[4];
+    const int64_t total = T.ball_start[T.n_jobs];
+    const double r2 = [&] {
+#pragma clang fp contract(off)
+        return r * r;
+    }();
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        const int jb = find_job(T.ball_start, T.n_jobs, w);
+        const BJob& J = T.jobs[jb];
+        const int mball = (int)(w - T.ball_start[jb]);
+        const subsurf4d_centre c = J.centres[mball];
+        int lo0, lo1, lo2, w0, w1;
+        int64_t count;
+        const bool ok = bball(J, c, r, lo0, lo1, lo2, w0, w1, count);
+        double mn = INFINITY, mx = -INFINITY, span = 0.0, mu = 0.0;
+        if (PHASE == 1 && ok) {
+            mu = J.ball[2 * mball];
+            span = J.ball[2 * mball + 1] - mu;
+        }
+        if (ok && !(PHASE == 1 && !(span >= 1e-12))) {
+            for (int64_t qq = threadIdx.x; qq < count; qq += blockDim.x) {
+                const int i = lo0 + (int)(qq % w0);
+                const int64_t q2 = qq / w0;
+                const int j = lo1 + (int)(q2 % w1);
+                const int k = lo2 + (int)(q2 / w1);
+                const double d2 = dist2_exact((double)(i - 1) - (double)c.x, (double)(j - 1) - (double)c.y,
+                                              (double)(k - 1) - (double)c.z);
+                if (!(d2 <= r2)) continue;
+                const int l = c.frame + 1;
+                const int64_t p = (((int64_t)l * J.p3 + k) * J.p2 + j) * J.p1 + i;
+                if (PHASE == 0) {
+                    const double v = J.u[p];
+                    mn = fmin(mn, v);
+                    mx = fmax(mx, v);
+                } else {
+                    const int64_t ii = (((int64_t)(l - 1) * J.n3 + (k - 1)) * J.n2 + (j - 1)) * J.n1 + (i - 1);
+                    if (J.owner[ii] == mball) J.u[p] = (J.u[p] - mu) / span;
+                }
+            }
+        }
+        if (PHASE == 0) {
+            mn = wave_min(mn);
+            mx = wave_max(mx);
+            if ((threadIdx.x & 63) == 0) { s_lo[threadIdx.x >> 6] = mn; s_hi[threadIdx.x >> 6] = mx; }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                J.ball[2 * mball] = fmin(fmin(s_lo[0], s_lo[1]), fmin(s_lo[2], s_lo[3]));
+                J.ball[2 * mball + 1] = fmax(fmax(s_hi[0], s_hi[1]), fmax(s_hi[2], s_hi[3]));
+            }
+            __syncthreads();
+        }
+    }
+}
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+// Workspace carving of one job in the batched layout.
+bool plan_batch_job(const int32_t n[4], int32_t nc, BJob* J, size_t* bytes)
+{
+    for (int d = 0; d < 4; ++d)
+        if (n[d] < 1 || n[d] > (1 << 16)) return false;
+    if ((int64_t)(n[0] + 2) * (n[1] + 2) * (n[2] + 2) * (n[3] + 2) >= ((int64_t)1 << 31)) return false;
+    BJob b{};
+    b.n1 = n[0]; b.n2 = n[1]; b.n3 = n[2]; b.n4 = n[3];
+    b.p1 = n[0] + 2; b.p2 = n[1] + 2; b.p3 = n[2] + 2; b.p4 = n[3] + 2;
+    b.half = (n[0] + 1) / 2;
+    b.rsu = b.half + 2;
+    b.nc = nc;
+    b.nrow_int = (int64_t)n[1] * n[2] * n[3];
+    b.nrow_pad = (int64_t)b.p2 * b.p3 * b.p4;
+    b.npad = (int64_t)b.p1 * b.nrow_pad;
+    b.nint = (int64_t)n[0] * b.nrow_int;
+    b.ncq = b.nrow_int * b.half;
+    b.ntq = (b.ncq + kTileSlots - 1) / kTileSlots;
+    b.nip = (b.npad + kItem - 1) / kItem;
+    b.nit = (b.ncq + kItem - 1) / kItem;
+    const int64_t parts = b.nip > 2 * b.nit ? b.nip : 2 * b.nit;
+    size_t off = 0;
+    auto take = [&](size_t nbytes) { const size_t o = off; off += al256(nbytes); return o; };
+    const size_t o_ctrl = take(sizeof(Ctrl));
+    const size_t o_pa = take(sizeof(double) * parts);
+    const size_t o_pb = take(sizeof(double) * parts);
+    const size_t o_ball = take(sizeof(double) * 2 * (size_t)(nc > 0 ? nc : 1));
+    const size_t o_xr = take(sizeof(double) * b.nrow_pad * b.rsu);
+    const size_t o_xb = take(sizeof(double) * b.nrow_pad * b.rsu);
+    const size_t o_coef = take(sizeof(double) * 2 * b.ntq * kTileVals);
+    const size_t o_c16 = take(16 * 2 * b.ntq * kTileSlots);
+    const size_t o_rf = take(sizeof(float) * 2 * b.ntq * kTileSlots);
+    const size_t o_dr = take(sizeof(float) * b.nrow_pad * b.rsu);
+    const size_t o_db = take(sizeof(float) * b.nrow_pad * b.rsu);
+    // offsets are stored as pointers relative to a null base until bound
+    b.C = reinterpret_cast<Ctrl*>(o_ctrl);
+    b.part_a = reinterpret_cast<double*>(o_pa);
+    b.part_b = reinterpret_cast<double*>(o_pb);
+    b.ball = reinterpret_cast<double*>(o_ball);
+    b.xr = reinterpret_cast<double*>(o_xr);
+    b.xb = reinterpret_cast<double*>(o_xb);
+    b.coef = reinterpret_cast<double*>(o_coef);
+    b.c16 = reinterpret_cast<uint4*>(o_c16);
+    b.rf = reinterpret_cast<float*>(o_rf);
+    b.dr = reinterpret_cast<float*>(o_dr);
+    b.db = reinterpret_cast<float*>(o_db);
+    *J = b;
+    *bytes = off;
+    return true;
+}
+
+size_t batch_job_bytes(const int32_t n[4], int32_t nc)
+{
+    BJob J;
+    size_t b = 0;
+    return plan_batch_job(n, nc, &J, &b) ? b : 0;
+}
+
+size_t batch_table_bytes(int32_t n_jobs)
+{
+    const size_t nj = (size_t)(n_jobs > 0 ? n_jobs : 1);
+    return al256(sizeof(BJob) * nj) + al256(sizeof(Ctrl) * nj) + 4 * al256(sizeof(int64_t) * (nj + 1)) + 256;
+}
+
+namespace {
+
+template <typename T>
+T* rebase(void* ws, T* off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + reinterpret_cast<size_t>(off)); }
+
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+namespace {
+
+// Graph capture is not allowed on the legacy default stream: a batched step
+// called on it runs on a library-owned non-blocking stream (default priority,
+// one per device), ordered after the caller's earlier work by an event; the
+// call synchronises before it returns.
+hipStream_t side_stream()
+{
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> g(mu);
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    streams[dev] = st;
+    return st;
+}
+
+}  // namespace
+
+int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf4d_step_params& sp,
+                      subsurf4d_result* results, void* table, size_t table_bytes, hipStream_t s);
+
+int run_batch_step(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf4d_step_params& sp,
+                   subsurf4d_result* results, void* table, size_t table_bytes, hipStream_t s)
+{
+    if (s != nullptr) return run_batch_step_on(jobs, n_jobs, sp, results, table, table_bytes, s);
+    hipStream_t w = side_stream();
+    if (!w) {
+        set_error("batched step: could not create a stream");
+        return SUBSURF4D_EDEVICE;
+    }
+    hipEvent_t ev;
+    SS4_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ev, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(w, ev, 0);
+    (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return hip_fail(e, "batched step: stream ordering");
+    return run_batch_step_on(jobs, n_jobs, sp, results, table, table_bytes, w);
+}
+
+int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf4d_step_params& sp,
+                      subsurf4d_result* results, void* table, size_t table_bytes, hipStream_t s)
+{
+    // host-side descriptors
+    std::vector<BJob> hj(n_jobs);
+    std::vector<int64_t> asm_start(n_jobs + 1), col_start(n_jobs + 1), both_start(n_jobs + 1), ball_start(n_jobs + 1);
+    asm_start[0] = col_start[0] = both_start[0] = ball_start[0] = 0;
+    for (int q = 0; q < n_jobs; ++q) {
+        const subsurf4d_batch_job& bj = jobs[q];
+        BJob J;
+        size_t need = 0;
+        const int nc = sp.rescale ? bj.n_centres : 0;
+        if (!plan_batch_job(bj.grid.n, nc, &J, &need)) {
+            set_error("batched step: unsupported grid");
+            return SUBSURF4D_ESHAPE;
+        }
+        if (bj.workspace_bytes < need) {
+            set_error("batched step: job workspace too small (see subsurf4d_batch_workspace_bytes)");
+            return SUBSURF4D_EWORKSPACE;
+        }
+        void* ws = bj.workspace;
+        J.C = rebase(ws, J.C);
+        J.part_a = rebase(ws, J.part_a);
+        J.part_b = rebase(ws, J.part_b);
+        J.ball = rebase(ws, J.ball);
+        J.xr = rebase(ws, J.xr);
+        J.xb = rebase(ws, J.xb);
+        J.coef = rebase(ws, J.coef);
+        J.c16 = rebase(ws, J.c16);
+        J.rf = rebase(ws, J.rf);
+        J.dr = rebase(ws, J.dr);
+        J.db = rebase(ws, J.db);
+        J.th2 = sp.tau / (bj.grid.h * bj.grid.h);
+        J.eps2 = sp.eps * sp.eps;
+        J.inv_h = 1.0 / bj.grid.h;
+        J.G = bj.G;
+        J.u = bj.u;
+        J.owner = bj.owner;
+        J.centres = bj.centres;
+        hj[q] = J;
+        asm_start[q + 1] = asm_start[q] + J.nip;
+        col_start[q + 1] = col_start[q] + J.nit;
+        both_start[q + 1] = both_start[q] + 2 * J.nit;
+        ball_start[q + 1] = ball_start[q] + J.nc;
+    }
+    if (table_bytes < batch_table_bytes(n_jobs)) {
+        set_error("batched step: table workspace too small (see subsurf4d_batch_table_bytes)");
+        return SUBSURF4D_EWORKSPACE;
+    }
+    char* tb = static_cast<char*>(table);
+    size_t off = 0;
+    BTable T{};
+    T.jobs = reinterpret_cast<BJob*>(tb + off); off += al256(sizeof(BJob) * n_jobs);
+    T.out = reinterpret_cast<Ctrl*>(tb + off); off += al256(sizeof(Ctrl) * n_jobs);
+    T.asm_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
+    T.col_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
+    T.both_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
+    T.ball_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
+    T.active = reinterpret_cast<int*>(tb + off);
+    T.pass = T.active + 1;
+    T.n_jobs = n_jobs;
+    const int m = sp.inner_sweeps;
+    T.max_outer = sp.max_iter / m > 1 ? sp.max_iter / m : 1;
+    T.omega = (float)sp.omega;
+    SS4_HIP(hipMemcpyAsync(T.jobs, hj.data(), sizeof(BJob) * n_jobs, hipMemcpyHostToDevice, s));
+    SS4_HIP(hipMemcpyAsync(T.asm_start, asm_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
+    SS4_HIP(hipMemcpyAsync(T.col_start, col_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
+    SS4_HIP(hipMemcpyAsync(T.both_start, both_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
+    SS4_HIP(hipMemcpyAsync(T.ball_start, ball_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
+
+    const int g_asm = resident_grid(reinterpret_cast<const void*>(&kb_assemble));
+    const int g_res = resident_grid(reinterpret_cast<const void*>(&kb_residual));
+    const int g_up = resident_grid(reinterpret_cast<const void*>(&kb_update));
+    const dim3 g_zero(64, n_jobs < 65535 ? n_jobs : 65535);
+
+    kb_init<<<(n_jobs + 255) / 256, 256, 0, s>>>(T, sp.refine_tol, T.max_outer);
+    const int g_dec = n_jobs < 4096 ? n_jobs : 4096;
+    kb_assemble<<<g_asm, kBlock, 0, s>>>(T);
+    kb_assemble_decide<<<g_dec, kBlock, 0, s>>>(T);
+    kb_zero_d<<<g_zero, 256, 0, s>>>(T);
+    SS4_LAUNCHED("batched: assemble");
+
+    // Launch-shape autotuner for the inner sweep: the first batch with a given
+    // signature times grids of 1, 2 and 4 times the resident size on its own
+    // data and keeps the fastest.  The grid only changes which block visits
+    // which work item, never a job's arithmetic; the corrections are zeroed
+    // again afterwards.
+    int g_sw = 0;
+    {
+        static std::mutex mu;
+        static std::map<std::pair<int, int64_t>, int> tuned;
+        const auto key = std::make_pair(n_jobs, col_start[n_jobs]);
+        {
+            std::lock_guard<std::mutex> g(mu);
+            auto it = tuned.find(key);
+            if (it != tuned.end()) g_sw = it->second;
+        }
+        if (!g_sw) {
+            const int res = resident_grid(reinterpret_cast<const void*>(&kb_sweep<0>));
+            hipEvent_t e0, e1;
+            SS4_HIP(hipEventCreate(&e0));
+            SS4_HIP(hipEventCreate(&e1));
+            float best = 1e30f;
+            for (int mult = 1; mult <= 4; mult *= 2) {
+                const int g = res * mult;
+                kb_sweep<0><<<g, kBlock, 0, s>>>(T);
+                SS4_HIP(hipEventRecord(e0, s));
+                for (int rep = 0; rep < 2; ++rep) {
+                    kb_sweep<0><<<g, kBlock, 0, s>>>(T);
+                    kb_sweep<1><<<g, kBlock, 0, s>>>(T);
+                }
+                SS4_HIP(hipEventRecord(e1, s));
+                SS4_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                SS4_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best) { best = ms; g_sw = g; }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            kb_zero_d<<<g_zero, 256, 0, s>>>(T);
+            SS4_LAUNCHED("batched: tuning");
+            std::lock_guard<std::mutex> g(mu);
+            tuned[key] = g_sw;
+        }
+    }
+
+    // one refinement pass = residual (decides), m inner iterations, update;
+    // captured once as a graph and replayed until every job has finished
+    const bool eager = (sp.flags & SUBSURF4D_FLAG_NO_GRAPH) != 0;
+    auto enqueue_pass = [&]() {
+        kb_residual<<<g_res, kBlock, 0, s>>>(T);
+        kb_residual_decide<<<g_dec, kBlock, 0, s>>>(T);
+        for (int it = 0; it < m; ++it) {
+            kb_sweep<0><<<g_sw, kBlock, 0, s>>>(T);
+            kb_sweep<1><<<g_sw, kBlock, 0, s>>>(T);
+        }
+        kb_update<<<g_up, kBlock, 0, s>>>(T);
+        kb_next_pass<<<1, 64, 0, s>>>(T);
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (!eager) {
+        SS4_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        enqueue_pass();
+        SS4_HIP(hipStreamEndCapture(s, &graph));
+        SS4_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+
+    int active = n_jobs;
+    SS4_HIP(hipMemcpyAsync(&active, T.active, sizeof(int), hipMemcpyDeviceToHost, s));
+    SS4_HIP(hipStreamSynchronize(s));
+    int passes = 0;
+    int rc = 0;
+    while (active > 0) {
+        if (passes > T.max_outer + 1) {
+            set_error("internal: batched refinement ended without a decision");
+            rc = SUBSURF4D_EDEVICE;
+            break;
+        }
+        hipError_t e = hipSuccess;
+        if (eager) {
+            enqueue_pass();
+            e = hipGetLastError();
+        } else {
+            e = hipGraphLaunch(exec, s);
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(&active, T.active, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) { rc = hip_fail(e, "batched: refinement pass"); break; }
+        ++passes;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc) return rc;
+
+    kb_unsplit<<<g_up, kBlock, 0, s>>>(T);
+    if (sp.rescale && ball_start[n_jobs] > 0) {
+        const int gb = (int)(ball_start[n_jobs] < 65536 ? ball_start[n_jobs] : 65536);
+        kb_rescale<0><<<gb, kBlock, 0, s>>>(T, sp.ball_r);
+        kb_rescale<1><<<gb, kBlock, 0, s>>>(T, sp.ball_r);
+    }
+    SS4_LAUNCHED("batched: unsplit / rescale");
+    // gather the outcomes
+    std::vector<Ctrl> hc(n_jobs);
+    kb_gather<<<(n_jobs + 255) / 256, 256, 0, s>>>(T);
+    SS4_HIP(hipMemcpyAsync(hc.data(), T.out, sizeof(Ctrl) * n_jobs, hipMemcpyDeviceToHost, s));
+    SS4_HIP(hipStreamSynchronize(s));
+    int worst = 0;
+    for (int q = 0; q < n_jobs; ++q) {
+        if (results) {
+            results[q].status = hc[q].status;
+            results[q].iterations = hc[q].outer * m;
+            results[q].outer_iterations = hc[q].outer;
+            results[q].reserved = 0;
+            results[q].rel_residual = hc[q].rel_res;
+            results[q].bnorm = hc[q].bn;
+        }
+        if (hc[q].status == SUBSURF4D_ENONFINITE) worst = SUBSURF4D_ENONFINITE;
+        else if (hc[q].status == SUBSURF4D_NOT_CONVERGED && worst == 0) worst = SUBSURF4D_NOT_CONVERGED;
+    }
+    if (worst == SUBSURF4D_ENONFINITE) {
+        set_error("batched step: a job hit a non-finite residual (see its result)");
+        return SUBSURF4D_ENONFINITE;
+    }
+    return worst;
+}
+
+}  // namespace ss4

@@ -78,6 +78,12 @@ int launch_assembly(const WsPlan& P, double h, const double* G, const double* w,
                     void* coef16, void* ws, hipStream_t s);
 int run_copy_probe(const void* src, void* dst, size_t bytes, int reps, double* ms, hipStream_t s);
 
+// batched windows (batch.hip)
+size_t batch_job_bytes(const int32_t n[4], int32_t nc);
+size_t batch_table_bytes(int32_t n_jobs);
+int run_batch_step(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf4d_step_params& sp,
+                   subsurf4d_result* results, void* table, size_t table_bytes, hipStream_t s);
+
 // mixed precision (mixed.hip)
 int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
                     const subsurf4d_step_params& sp, subsurf4d_result* res, void* ws,

@@ -399,7 +399,8 @@ int lhe_solve(const WsPlan& P, double a, double omega, double tol, int max_iter,
     double* pa = ws_ptr<double>(ws, P.part_a);
     double* pb = ws_ptr<double>(ws, P.part_b);
     const int gs = grid_for(L.nint);
-    const int gr = grid_for(L.nint);
+    // few blocks for the residual: each block ends with one device-scope fence
+    const int gr = grid_for(L.nint) < 256 ? grid_for(L.nint) : 256;
     k_copy_f64<<<grid_for(L.nint), kBlock, 0, s>>>(rhs, J, L.nint);
     k_ctrl_init<<<1, 64, 0, s>>>(C, tol, max_iter);
     k_lhe_residual<<<gr, kBlock, 0, s>>>(L, a, rhs, J, 0, pa, pb, C);
@@ -465,10 +466,16 @@ int run_prepare(const WsPlan& P, double h, const void* image, int dtype, const s
     double* src1 = ITH;
     double* dst1 = S1;
     const double a = pp.smooth_tau / (h * h);
+    // omega <= 0: Young's optimum for the interior Jacobi radius 2*dim*a/(1+2*dim*a)
+    double omega = pp.smooth_omega;
+    if (!(omega > 0.0)) {
+        const double rho = 8.0 * a / (1.0 + 8.0 * a);
+        omega = 2.0 / (1.0 + sqrt(1.0 - rho * rho));
+    }
     for (int step = 0; step < pp.smooth_steps; ++step) {
-        int rc = lhe_solve(P, a, pp.smooth_omega, pp.smooth_tol, pp.smooth_max_iter, src0, dst0, ws, s, &status);
+        int rc = lhe_solve(P, a, omega, pp.smooth_tol, pp.smooth_max_iter, src0, dst0, ws, s, &status);
         if (rc) return rc;
-        rc = lhe_solve(P, a, pp.smooth_omega, pp.smooth_tol, pp.smooth_max_iter, src1, dst1, ws, s, &status);
+        rc = lhe_solve(P, a, omega, pp.smooth_tol, pp.smooth_max_iter, src1, dst1, ws, s, &status);
         if (rc) return rc;
         double* t0 = src0; src0 = dst0; dst0 = t0;
         double* t1 = src1; src1 = dst1; dst1 = t1;

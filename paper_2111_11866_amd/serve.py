@@ -1,0 +1,213 @@
+"""Serving loop for per-nucleus window segmentation jobs.
+
+A job is one 4D window (the paper cuts small windows around nuclei, Sec. 4)
+with its seed track: preparation (thresholding, presmoothing, edge detector),
+initial function and local rescale, then `steps` semi-implicit time steps;
+the result is the final u, copied to the host.
+
+BatchServer: continuous batching.  Jobs that arrive while others run are
+admitted, first come first served, as soon as their device memory fits the
+HBM budget; an admitted job keeps G, u and its workspace resident until it
+finishes.  Every loop iteration advances all admitted jobs by one time step
+with one batched call (mixed precision, graph-replayed refinement passes), so
+the work of all resident jobs overlaps on the device; finished jobs hand
+their result to the host and free their memory at the step boundary.
+
+PlainServer: the same jobs, first come first served, one at a time, each step
+an FP64 subsurf4d_step on its own (the plain per-job GPU path).
+
+Latency is measured from a job's arrival time to the moment its result is on
+the host.  All numerics run in libsubsurf4d.so; this module only schedules.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field, replace
+
+import numpy as np
+
+from paper_2111_11866_amd import binding as B
+
+MAX_WINDOW = (96, 96, 96, 12)
+
+
+@dataclass
+class Window:
+    jid: int
+    arrival: float
+    img: object                # synth.Image4D (host)
+    steps_done: int = 0
+    state: object = None       # binding.Job once admitted
+    nbytes: int = 0
+    admitted: float = 0.0
+    finished: float = 0.0
+    result: np.ndarray = None
+    rel_res: list = field(default_factory=list)
+
+
+def window_bytes(n, nc):
+    """Device bytes one admitted window holds (batched layout)."""
+    pad = int(np.prod([v + 2 for v in n]))
+    nint = int(np.prod(n))
+    return B.batch_workspace_bytes(n, nc) + 40 * pad + 5 * nint + 16 * max(nc, 1)
+
+
+class _Shared:
+    """Preparation workspace and batch table shared by all jobs of a server."""
+
+    def __init__(self, max_jobs, device="cuda"):
+        import torch
+
+        self.prep_ws = torch.empty(B.prepare_workspace_bytes(MAX_WINDOW, 2 * MAX_WINDOW[3]),
+                                   dtype=torch.uint8, device=device)
+        self.table = torch.empty(B.batch_table_bytes(max_jobs), dtype=torch.uint8, device=device)
+        self.max_jobs = max_jobs
+
+
+def admit_window(w: Window, pp, v, R, ball_r, shared: _Shared, batch=True, precision=B.MIXED):
+    img = w.img
+    if any(a > b for a, b in zip(img.n, MAX_WINDOW)):
+        raise ValueError(f"window {img.n} exceeds {MAX_WINDOW}")
+    job = B.Job(img.n, img.image, img.centres, img.seeds, batch=batch, shared_ws=shared.prep_ws,
+                precision=precision)
+    job.prepare(pp)
+    job.init(v=v, R=R, ball_r=ball_r)
+    w.state = job
+    return job
+
+
+class BatchServer:
+    def __init__(self, pp: B.PrepareParams, sp: B.StepParams, steps=20, hbm_budget=64 << 30,
+                 max_jobs=4096, v=1.0, R=0.0):
+        assert sp.precision == B.MIXED
+        self.pp, self.sp, self.steps = pp, sp, steps
+        self.budget, self.v, self.R = hbm_budget, v, R
+        self.shared = _Shared(max_jobs)
+
+    def run(self, windows, realtime=True, log=None):
+        """Serve `windows` (arrival times in seconds from the start).  Returns stats."""
+        import torch
+
+        pending = deque(sorted(windows, key=lambda w: w.arrival))
+        running, done = [], []
+        used = 0
+        t0 = time.perf_counter()
+        steps_run = 0
+        max_conc = 0
+        while pending or running:
+            now = time.perf_counter() - t0
+            if not realtime:
+                now = max(now, pending[0].arrival if pending and not running else now)
+            # admit arrived jobs in order while they fit the budget and the table
+            while pending and pending[0].arrival <= now and len(running) < self.shared.max_jobs:
+                w = pending[0]
+                need = window_bytes(w.img.n, len(w.img.centres))
+                if used + need > self.budget and running:
+                    break
+                pending.popleft()
+                w.nbytes = need
+                used += need
+                admit_window(w, self.pp, self.v, self.R, self.sp.ball_r, self.shared)
+                w.admitted = time.perf_counter() - t0
+                running.append(w)
+            if not running:
+                if pending:
+                    wait = pending[0].arrival - (time.perf_counter() - t0)
+                    if wait > 0 and realtime:
+                        time.sleep(min(wait, 0.05))
+                continue
+            max_conc = max(max_conc, len(running))
+            jobs = [w.state for w in running]
+            rc, res = B.step_batched(jobs, self.sp, self.shared.table)
+            if rc < 0 or any(r["status"] < 0 for r in res):
+                raise RuntimeError(f"batched step failed: {rc} {res}")
+            steps_run += 1
+            still = []
+            for w, r in zip(running, res):
+                w.steps_done += 1
+                w.rel_res.append(r["rel_res"])
+                if w.steps_done >= self.steps:
+                    w.result = w.state.u.cpu().numpy()        # synchronous copy: result on the host
+                    w.finished = time.perf_counter() - t0
+                    used -= w.nbytes
+                    w.state = None
+                    done.append(w)
+                else:
+                    still.append(w)
+            running = still
+            if log and steps_run % 20 == 0:
+                log(f"[serve] t={time.perf_counter() - t0:.2f}s running {len(running)} done {len(done)} "
+                    f"pending {len(pending)}")
+        torch.cuda.synchronize()
+        return summarize(done, time.perf_counter() - t0, extra=dict(batched_steps=steps_run,
+                                                                  max_concurrent=max_conc))
+
+
+class PlainServer:
+    """First come first served, one job at a time, FP64 per-job steps."""
+
+    def __init__(self, pp: B.PrepareParams, sp: B.StepParams, steps=20, v=1.0, R=0.0):
+        assert sp.precision == B.FP64
+        self.pp, self.sp, self.steps, self.v, self.R = pp, sp, steps, v, R
+        self.shared = _Shared(1)
+
+    def run(self, windows, realtime=True, log=None, max_seconds=None):
+        import torch
+
+        pending = deque(sorted(windows, key=lambda w: w.arrival))
+        done = []
+        t0 = time.perf_counter()
+        while pending:
+            now = time.perf_counter() - t0
+            if max_seconds is not None and now > max_seconds:
+                break
+            w = pending[0]
+            if w.arrival > now and realtime:
+                time.sleep(min(w.arrival - now, 0.05))
+                continue
+            pending.popleft()
+            w.admitted = time.perf_counter() - t0
+            job = B.Job(w.img.n, w.img.image, w.img.centres, w.img.seeds, shared_ws=None, precision=B.FP64)
+            job.prepare(self.pp)
+            job.init(v=self.v, R=self.R, ball_r=self.sp.ball_r)
+            for _ in range(self.steps):
+                r = job.step(self.sp)
+                w.rel_res.append(r["rel_res"])
+            w.result = job.u.cpu().numpy()
+            w.finished = time.perf_counter() - t0
+            done.append(w)
+            del job
+        torch.cuda.synchronize()
+        return summarize(done, time.perf_counter() - t0, extra=dict(unserved=len(pending)))
+
+
+def summarize(done, makespan, extra=None):
+    lat = np.array([w.finished - w.arrival for w in done]) if done else np.zeros(1)
+    out = dict(jobs=len(done), makespan_s=makespan,
+               jobs_per_s=len(done) / makespan if makespan > 0 else 0.0,
+               p50_latency_s=float(np.percentile(lat, 50)), p99_latency_s=float(np.percentile(lat, 99)),
+               mean_latency_s=float(lat.mean()))
+    if extra:
+        out.update(extra)
+    return out
+
+
+def make_windows(rate, count, first_job=0, seed=7):
+    """Poisson arrival stream of window jobs (images drawn up front)."""
+    import synth
+
+    t, sizes = synth.serving_stream(rate, count, seed=seed, first_job=first_job)
+    wins = []
+    for q, (ta, n) in enumerate(zip(t, sizes)):
+        j = first_job + q
+        img = synth.window_job(n, 200000 + j, 300000 + j)
+        wins.append(Window(jid=j, arrival=float(ta), img=img))
+    return wins
+
+
+def default_params():
+    pp = B.PrepareParams(image_scale=1.0 / 255.0)
+    plain = B.StepParams(eps=1e-3, tau=0.5, omega=1.5, tol=1e-8)
+    mixed = replace(plain, precision=B.MIXED, refine_tol=1e-8, inner_sweeps=8)
+    return pp, plain, mixed

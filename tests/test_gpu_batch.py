@@ -1,0 +1,123 @@
+"""Batched step over many uneven windows (mixed precision, graph-replayed
+refinement passes) against the FP64 oracle, the single-job path, and itself
+(alone vs in a mix, graph vs eager launches)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import oracle as orc  # noqa: E402
+import synth  # noqa: E402
+from paper_2111_11866_amd import binding as B  # noqa: E402
+
+SP = B.StepParams(precision=B.MIXED, refine_tol=1e-10, inner_sweeps=8)
+PP = B.PrepareParams(image_scale=1.0 / 255.0)
+
+
+def H(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def make_jobs(sizes, seed0=1000, prep_ws=None):
+    jobs = []
+    for q, n in enumerate(sizes):
+        img = synth.window_job(n, seed0 + q, seed0 + 100000 + q)
+        j = B.Job(n, img.image, img.centres, img.seeds, precision=B.MIXED, batch=True, shared_ws=prep_ws)
+        j.prepare(PP)
+        j.init(v=1.0, R=8.0, ball_r=SP.ball_r)
+        j.img = img
+        jobs.append(j)
+    return jobs
+
+
+SIZES = [(24, 30, 26, 3), (33, 25, 28, 5), (40, 40, 40, 5), (27, 35, 24, 9), (64, 24, 30, 4), (25, 25, 25, 3)]
+
+
+@pytest.fixture(scope="module")
+def batch():
+    jobs = make_jobs(SIZES)
+    u0 = [j.u.clone() for j in jobs]
+    return jobs, u0
+
+
+def run(jobs, sp=SP):
+    table = torch.empty(B.batch_table_bytes(len(jobs)), dtype=torch.uint8, device="cuda")
+    return B.step_batched(jobs, sp, table)
+
+
+def test_batched_matches_oracle_and_single_job(batch):
+    jobs, u0 = batch
+    for j, u in zip(jobs, u0):
+        j.u.copy_(u)
+    rc, res = run(jobs)
+    assert rc == 0
+    for q, j in enumerate(jobs):
+        assert res[q]["status"] == 0 and res[q]["rel_res"] <= 1e-10
+        w = H(u0[q])
+        G, owner = H(j.G), H(j.owner)
+        ref = orc.step(j.n, G, w, j.img.centres, owner, orc.StepParams(tol=1e-14), orc.RB)
+        got = H(j.u)
+        err = np.abs(got - ref["u_resc"]).max() / max(np.abs(ref["u_resc"]).max(), 1e-300)
+        assert err <= 1e-6, (q, err)
+        # the single-job mixed path on the same input
+        us = u0[q].clone()
+        r1 = B.step(j.n, j.h, j.G, j.centres, j.nc, j.owner, us, SP, j.ws)
+        assert r1["status"] == 0
+        assert np.abs(H(us) - got).max() <= 1e-8
+
+
+def test_batched_alone_equals_in_mix(batch):
+    """Each window's result is bitwise the same alone and inside the batch."""
+    jobs, u0 = batch
+    for j, u in zip(jobs, u0):
+        j.u.copy_(u)
+    run(jobs)
+    mixed = [H(j.u) for j in jobs]
+    for q in (0, 3, 5):
+        jobs[q].u.copy_(u0[q])
+        rc, res = run([jobs[q]])
+        assert np.array_equal(H(jobs[q].u), mixed[q]), q
+
+
+def test_graph_replays_equal_eager(batch):
+    """Refinement passes replayed from a captured graph give the same bits as
+    the same kernels launched one by one (several replays per step)."""
+    jobs, u0 = batch
+    out = []
+    for flags in (0, B.FLAG_NO_GRAPH, 0):
+        for j, u in zip(jobs, u0):
+            j.u.copy_(u)
+        from dataclasses import replace
+        rc, res = run(jobs, replace(SP, flags=flags))
+        assert all(r["outer"] >= 2 for r in res)
+        out.append([H(j.u) for j in jobs])
+    for a, b, c in zip(*out):
+        assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_batched_several_steps_stay_bounded(batch):
+    jobs, u0 = batch
+    for j, u in zip(jobs, u0):
+        j.u.copy_(u)
+    for s in range(5):
+        rc, res = run(jobs)
+        assert rc == 0
+    for j in jobs:
+        u = H(j.u)
+        assert u.min() >= -1e-9 and u.max() <= 1 + 1e-9
+
+
+def test_batched_tau_zero_and_not_converged():
+    jobs = make_jobs([(26, 24, 25, 3), (30, 28, 24, 4)], seed0=5000)
+    before = [H(j.u) for j in jobs]
+    from dataclasses import replace
+    rc, res = run(jobs, replace(SP, tau=0.0, rescale=False))
+    assert rc == 0 and all(r["outer"] == 0 for r in res)
+    for j, b in zip(jobs, before):
+        assert np.array_equal(H(j.u), b)
+    rc, res = run(jobs, replace(SP, refine_tol=1e-16, inner_sweeps=2, max_iter=4))
+    assert rc == B.NOT_CONVERGED and all(r["status"] == B.NOT_CONVERGED for r in res)

@@ -1,0 +1,40 @@
+"""Continuous-batching server: results are the same alone and in the mix,
+and agree with the plain per-job FP64 path within 1e-6 relative."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+from paper_2111_11866_amd import serve as S  # noqa: E402
+
+
+def test_serving_mix_alone_and_plain():
+    pp, plain, mixed = S.default_params()
+    wins = S.make_windows(2000.0, 24)
+    stats = S.BatchServer(pp, mixed, steps=4, hbm_budget=8 << 30).run(wins)
+    assert stats["jobs"] == 24 and stats["max_concurrent"] >= 2
+    for q in (0, 7, 23):
+        alone = S.make_windows(2000.0, 24)[q]
+        alone.arrival = 0.0
+        S.BatchServer(pp, mixed, steps=4, hbm_budget=8 << 30).run([alone])
+        assert np.array_equal(alone.result, wins[q].result), q
+        ref = S.make_windows(2000.0, 24)[q]
+        ref.arrival = 0.0
+        S.PlainServer(pp, plain, steps=4).run([ref])
+        scale = np.abs(ref.result).max()
+        assert np.abs(ref.result - wins[q].result).max() <= 1e-6 * scale
+
+
+def test_serving_budget_makes_jobs_wait_none_dropped():
+    pp, plain, mixed = S.default_params()
+    wins = S.make_windows(5000.0, 16)
+    # a budget below any single window: a job is still admitted when nothing
+    # else runs, so the jobs run one after another and none is dropped
+    stats = S.BatchServer(pp, mixed, steps=2, hbm_budget=1).run(wins)
+    assert stats["jobs"] == 16 and stats["max_concurrent"] == 1
+    two = sorted(S.window_bytes(w.img.n, len(w.img.centres)) for w in wins)[:2]
+    stats = S.BatchServer(pp, mixed, steps=2, hbm_budget=sum(two) + 1).run(S.make_windows(5000.0, 16))
+    assert stats["jobs"] == 16 and stats["max_concurrent"] <= 2
