@@ -257,7 +257,10 @@ typedef struct {
     size_t workspace_bytes;
 } subsurf4d_batch_job;
 
-/* Bytes of per-job workspace of the batched step (host-only; 0 if invalid). */
+/* Bytes of per-job workspace of the batched step (host-only; 0 if invalid).
+ * A batched job is a window: (N1+2)(N2+2)(N3+2)(N4+2) <= 2^25 padded cells
+ * (larger volumes go through subsurf4d_step); larger grids give 0 here and
+ * SUBSURF4D_ESHAPE from subsurf4d_step_batched. */
 size_t subsurf4d_batch_workspace_bytes(const subsurf4d_grid* grid, int32_t n_centres);
 
 /* Bytes of the shared device table of a batch of n_jobs jobs (host-only). */

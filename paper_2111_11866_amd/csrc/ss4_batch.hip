@@ -11,10 +11,13 @@
 // BF16 records and r/D are dense in q.  Small windows waste no lanes on row
 // padding: 256 consecutive q of one colour form a work item.
 //
-// Every launch walks a global list of work items of all unfinished jobs with
-// a resident-size grid.  Each job reduces its own per-item partial sums in a
-// fixed order when its last item arrives, so a job's result does not depend
-// on which other jobs share the launch.
+// Every launch walks a global list of work items with a resident-size grid,
+// each XCD a contiguous chunk of it in rounds.  The refinement kernels walk a list
+// compacted to the unfinished jobs after every stopping decision, so the
+// remaining work of the slow jobs is spread over the whole device.  Each job
+// reduces its own per-item partial sums in a fixed order in a kernel of its
+// own, so a job's result does not depend on which other jobs share the launch
+// or on which block visits which item.
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -32,6 +35,7 @@ struct BJob {
     int64_t ncq;          // flat cells of one colour (incl. inactive slots)
     int64_t ntq;          // 128-tiles of one colour
     int64_t nip, nit;     // items over padded cells / over one colour
+    uint64_t mg_half, mg_n2, mg_n3, mg_p1, mg_p2, mg_p3;   // ceil(2^63 / d) for the index divisions
     double th2, eps2, inv_h;
     const double* G;
     double* u;
@@ -44,7 +48,7 @@ struct BJob {
     float* rf;
     float* dr;
     float* db;
-    double* part_a;       // per-item partials (>= max(nip, 2*nit))
+    double* part_a;       // per-wave partials (>= kWaves * max(nip, 2*nit))
     double* part_b;
     double* ball;         // mu, xi per centre
     Ctrl* C;
@@ -59,6 +63,10 @@ struct BTable {
     int64_t* ball_start;  // prefix of nc
     int* active;          // jobs not finished
     int* pass;            // refinement pass counter (device, for graph replay)
+    int* n_act;           // length of the compacted list of unfinished jobs
+    int* act_jobs;        // unfinished jobs, in job order
+    int64_t* act_col;     // prefix of nit over act_jobs
+    int64_t* act_both;    // prefix of 2*nit over act_jobs
     int n_jobs;
     int max_outer;
     float omega;
@@ -68,6 +76,30 @@ struct BTable {
 namespace {
 
 constexpr int kItem = 256;
+constexpr int64_t kBatchMaxPadded = (int64_t)1 << 25;   // padded cells of one batched job
+constexpr int kWaves = kItem / 64;      // per-wave partial sums per work item
+
+#define SS4_GLOBAL __attribute__((address_space(1)))
+
+// Global-memory view of a pointer: with a wave-uniform base the loads and
+// stores take a 32-bit per-lane offset (every per-job array of the batched
+// layout stays below 4 GiB).
+template <typename T>
+__device__ __forceinline__ SS4_GLOBAL T* gbl(T* p) { return (SS4_GLOBAL T*)p; }
+
+// 16-byte record of the BF16 coefficients as a plain vector (HIP's uint4 is
+// a class that does not bind to global-address-space references)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// floor(n / d) for n < 2^31 with M = ceil(2^63 / d): n*M/2^63 exceeds n/d by
+// less than 2^-32, and the fractional part of n/d is at most 1 - 1/d, so the
+// floor is exact for every d < 2^32.
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint64_t M)
+{
+    const uint64_t lo = (uint64_t)n * (uint32_t)M;
+    const uint64_t mid = (uint64_t)n * (uint32_t)(M >> 32) + (lo >> 32);
+    return (uint32_t)(mid >> 31);
+}
 
 __device__ __forceinline__ int find_job(const int64_t* start, int n, int64_t w)
 {
@@ -80,56 +112,65 @@ __device__ __forceinline__ int find_job(const int64_t* start, int n, int64_t w)
     return lo;
 }
 
-// Contiguous range of work items of this block (one binary search per block,
-// then a linear walk through the job prefix array): consecutive items of a job
-// stay on one block, which keeps its neighbour rows warm in cache.
-struct ItemWalk {
-    int64_t w, end;
-    int jb;
-    const int64_t* start;
-    __device__ ItemWalk(const int64_t* st, int n_jobs) : start(st)
-    {
-        const int64_t total = st[n_jobs];
-        const int64_t per = (total + gridDim.x - 1) / gridDim.x;
-        w = (int64_t)blockIdx.x * per;
-        end = w + per < total ? w + per : total;
-        jb = w < end ? find_job(st, n_jobs, w) : 0;
+// Work items of a global list (prefix `st` over `n` entries; entry a is job
+// map[a], or a without a map) dealt to the blocks per XCD: the list is cut
+// into one contiguous chunk per XCD (blocks are placed on the XCDs round
+// robin), and in each round the blocks of one XCD take consecutive items of
+// its chunk.  Rows that an item reads as neighbours (the rows beside it and
+// the planes and frames before and after it) belong to items that the same
+// XCD processes in the same or an adjacent round, so they are still in that
+// XCD's L2.  Calls body(job, first, last, step) for each job's run of this
+// block's items first, first+step, ... < last.
+template <typename Body>
+__device__ __forceinline__ void for_runs(const int64_t* st, const int* map, int n, Body&& body)
+{
+    const int64_t total = st[n];
+    const int nx = (int)gridDim.x < kXcd ? (int)gridDim.x : kXcd;
+    const int slots = (int)gridDim.x / nx;
+    if ((int)blockIdx.x >= nx * slots) return;
+    const int64_t chunk = (total + nx - 1) / nx;
+    const int64_t beg = (int64_t)(blockIdx.x % nx) * chunk;
+    const int64_t end = beg + chunk < total ? beg + chunk : total;
+    int64_t w = beg + blockIdx.x / nx;
+    if (w >= end) return;
+    int a = find_job(st, n, w);
+    while (w < end) {
+        while (st[a + 1] <= w) ++a;
+        const int64_t base = st[a];
+        const int64_t stop = st[a + 1] < end ? st[a + 1] : end;
+        body(map ? map[a] : a, (uint32_t)(w - base), (uint32_t)(stop - base), (uint32_t)slots);
+        w += (stop - w + slots - 1) / slots * slots;      // first item of this block at or after stop
     }
-    __device__ bool next()
-    {
-        if (w >= end) return false;
-        while (start[jb + 1] <= w) ++jb;
-        return true;
-    }
+}
+
+__device__ __forceinline__ uint32_t bctile(const BJob& J, int colour, uint32_t q)
+{
+    return (((uint32_t)colour * (uint32_t)J.ntq + (q >> kTileShift)) * kTileFields) * kTileSlots +
+           (q & (kTileSlots - 1));
+}
+
+// One cell of colour `colour` in the flat numbering: q = r*half + m with r the
+// interior row (j,k,l) and m the slot; prow is the padded row index.
+struct Cell {
+    uint32_t prow;
+    int m, j, k, l, par;
 };
 
-__device__ __forceinline__ int64_t bprow(const BJob& J, int j, int k, int l)
-{
-    return ((int64_t)l * J.p3 + k) * J.p2 + j;
-}
-
-__device__ __forceinline__ int64_t bctile(const BJob& J, int colour, int64_t q)
-{
-    return (((int64_t)colour * J.ntq + (q >> kTileShift)) * kTileFields) * kTileSlots + (q & (kTileSlots - 1));
-}
-
 // decode flat q of colour `colour`: returns false for an inactive slot
-__device__ __forceinline__ bool bdecode(const BJob& J, int colour, int64_t q, int64_t& r, int& m, int& j, int& k,
-                                        int& l, int& par)
+__device__ __forceinline__ bool bdecode(const BJob& J, int colour, uint32_t q, Cell& c)
 {
-    if (q >= J.ncq) return false;
-    const uint32_t q32 = (uint32_t)q;                    // per-job sizes stay below 2^31 cells
-    const uint32_t r32 = q32 / (uint32_t)J.half;
-    m = (int)(q32 - r32 * (uint32_t)J.half);
-    const uint32_t r2 = r32 / (uint32_t)J.n2;
-    j = (int)(r32 - r2 * (uint32_t)J.n2) + 1;
-    const uint32_t r3 = r2 / (uint32_t)J.n3;
-    k = (int)(r2 - r3 * (uint32_t)J.n3) + 1;
-    l = (int)r3 + 1;
-    r = r32;
-    par = (colour + j + k + l) & 1;
-    const int cnt = par ? (J.n1 + 1) >> 1 : J.n1 >> 1;
-    return m < cnt;
+    if (q >= (uint32_t)J.ncq) return false;
+    const uint32_t r = fdiv(q, J.mg_half);
+    c.m = (int)(q - r * (uint32_t)J.half);
+    const uint32_t r2 = fdiv(r, J.mg_n2);
+    c.j = (int)(r - r2 * (uint32_t)J.n2) + 1;
+    const uint32_t r3 = fdiv(r2, J.mg_n3);
+    c.k = (int)(r2 - r3 * (uint32_t)J.n3) + 1;
+    c.l = (int)r3 + 1;
+    c.par = (colour + c.j + c.k + c.l) & 1;
+    c.prow = ((uint32_t)c.l * (uint32_t)J.p3 + (uint32_t)c.k) * (uint32_t)J.p2 + (uint32_t)c.j;
+    const int cnt = c.par ? (J.n1 + 1) >> 1 : J.n1 >> 1;
+    return c.m < cnt;
 }
 
 __global__ void kb_init(BTable T, double tol, int max_outer)
@@ -156,93 +197,107 @@ __global__ void kb_init(BTable T, double tol, int max_outer)
 // Assembly of every job (one thread per padded cell), writing the flat layout.
 __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
 {
-    __shared__ double lds[4];
-    for (ItemWalk it(T.asm_start, T.n_jobs); it.next(); ++it.w) {
-        const int jb = it.jb;
-        const BJob& J = T.jobs[jb];
-        const int64_t item = it.w - T.asm_start[jb];
-        const int64_t p = item * kItem + threadIdx.x;
-        double acc_b = 0.0, acc_r = 0.0;
-        if (p < J.npad) {
-            const int i = (int)(p % J.p1);
-            const int64_t prow = p / J.p1;
-            const int j = (int)(prow % J.p2);
-            const int64_t t2 = prow / J.p2;
-            const int k = (int)(t2 % J.p3);
-            const int l = (int)(t2 / J.p3);
-            const int colour = (i + j + k + l) & 1;
-            const int m = (i - 1) >> 1;
-            const double w0 = J.u[p];
-            const int64_t us = prow * J.rsu + 1 + m;
-            if (colour == 0) J.xr[us] = w0;
-            else J.xb[us] = w0;
-            const bool inside = i >= 1 && i <= J.n1 && j >= 1 && j <= J.n2 && k >= 1 && k <= J.n3 && l >= 1 && l <= J.n4;
-            if (inside) {
-                const int64_t sd[4] = {1, J.p1, (int64_t)J.p1 * J.p2, (int64_t)J.p1 * J.p2 * J.p3};
-                const int idx[4] = {i, j, k, l};
-                const int nn[4] = {J.n1, J.n2, J.n3, J.n4};
-                double wm[4], wp[4], q[8];
+    for_runs(T.asm_start, nullptr, T.n_jobs, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
+        const BJob J = T.jobs[jb];
+        SS4_GLOBAL const double* u = gbl(static_cast<const double*>(J.u));
+        SS4_GLOBAL const double* G = gbl(J.G);
+        SS4_GLOBAL double* xr = gbl(J.xr);
+        SS4_GLOBAL double* xb = gbl(J.xb);
+        SS4_GLOBAL double* coef = gbl(J.coef);
+        SS4_GLOBAL u32x4* c16 = gbl(reinterpret_cast<u32x4*>(J.c16));
+        SS4_GLOBAL double* pa = gbl(J.part_a);
+        SS4_GLOBAL double* pb = gbl(J.part_b);
+        const uint32_t npad = (uint32_t)J.npad;
+        const uint32_t sd[4] = {1u, (uint32_t)J.p1, (uint32_t)J.p1 * J.p2, (uint32_t)J.p1 * J.p2 * J.p3};
+        const int nn[4] = {J.n1, J.n2, J.n3, J.n4};
+        for (uint32_t item = i0; item < i1; item += step) {
+            const uint32_t p = item * kItem + threadIdx.x;
+            double acc_b = 0.0, acc_r = 0.0;
+            if (p < npad) {
+                const uint32_t prow = fdiv(p, J.mg_p1);
+                const int i = (int)(p - prow * (uint32_t)J.p1);
+                const uint32_t t2 = fdiv(prow, J.mg_p2);
+                const int j = (int)(prow - t2 * (uint32_t)J.p2);
+                const uint32_t t3 = fdiv(t2, J.mg_p3);
+                const int k = (int)(t2 - t3 * (uint32_t)J.p3);
+                const int l = (int)t3;
+                const int colour = (i + j + k + l) & 1;
+                const int m = (i - 1) >> 1;
+                const double w0 = u[p];
+                const uint32_t us = prow * (uint32_t)J.rsu + 1 + m;
+                if (colour == 0) xr[us] = w0;
+                else xb[us] = w0;
+                const bool inside =
+                    i >= 1 && i <= J.n1 && j >= 1 && j <= J.n2 && k >= 1 && k <= J.n3 && l >= 1 && l <= J.n4;
+                if (inside) {
+                    const int idx[4] = {i, j, k, l};
+                    double wm[4], wp[4], q[8];
 #pragma unroll
-                for (int d = 0; d < 4; ++d) { wm[d] = J.u[p - sd[d]]; wp[d] = J.u[p + sd[d]]; }
+                    for (int d = 0; d < 4; ++d) { wm[d] = u[p - sd[d]]; wp[d] = u[p + sd[d]]; }
 #pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    const double gnm = (w0 - wm[d]) * J.inv_h;
-                    const double gnp = (wp[d] - w0) * J.inv_h;
-                    double qm = gnm * gnm, qp = gnp * gnp;
+                    for (int d = 0; d < 4; ++d) {
+                        const double gnm = (w0 - wm[d]) * J.inv_h;
+                        const double gnp = (wp[d] - w0) * J.inv_h;
+                        double qm = gnm * gnm, qp = gnp * gnp;
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        if (t == d) continue;
-                        const double wpt = J.u[p + sd[t]], wmt = J.u[p - sd[t]];
-                        const double dm_pt = J.u[p - sd[d] + sd[t]], dm_mt = J.u[p - sd[d] - sd[t]];
-                        const double dp_pt = J.u[p + sd[d] + sd[t]], dp_mt = J.u[p + sd[d] - sd[t]];
-                        const double tm = ((dm_pt + wpt) - (dm_mt + wmt)) * (0.25 * J.inv_h);
-                        const double tp = ((wpt + dp_pt) - (wmt + dp_mt)) * (0.25 * J.inv_h);
-                        qm += tm * tm;
-                        qp += tp * tp;
+                        for (int t = 0; t < 4; ++t) {
+                            if (t == d) continue;
+                            const double wpt = wp[t], wmt = wm[t];
+                            const double dm_pt = u[p - sd[d] + sd[t]], dm_mt = u[p - sd[d] - sd[t]];
+                            const double dp_pt = u[p + sd[d] + sd[t]], dp_mt = u[p + sd[d] - sd[t]];
+                            const double tm = ((dm_pt + wpt) - (dm_mt + wmt)) * (0.25 * J.inv_h);
+                            const double tp = ((wpt + dp_pt) - (wmt + dp_mt)) * (0.25 * J.inv_h);
+                            qm += tm * tm;
+                            qp += tp * tp;
+                        }
+                        q[2 * d] = qm;
+                        q[2 * d + 1] = qp;
                     }
-                    q[2 * d] = qm;
-                    q[2 * d + 1] = qp;
+                    double qs = 0.0;
+#pragma unroll
+                    for (int f = 0; f < 8; ++f) qs += q[f];
+                    const double scale = J.th2 * sqrt(J.eps2 + qs / 8.0);
+                    double c[8];
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        c[2 * d] = scale * G[(uint32_t)d * npad + p - sd[d]] / sqrt(J.eps2 + q[2 * d]);
+                        c[2 * d + 1] = scale * G[(uint32_t)d * npad + p] / sqrt(J.eps2 + q[2 * d + 1]);
+                    }
+                    double D = 1.0, bfull = w0, off = 0.0;
+#pragma unroll
+                    for (int f = 0; f < 8; ++f) D += c[f];
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        off += c[2 * d] * wm[d] + c[2 * d + 1] * wp[d];
+                        if (idx[d] == 1) bfull += c[2 * d] * wm[d];
+                        if (idx[d] == nn[d]) bfull += c[2 * d + 1] * wp[d];
+                    }
+                    const double r0 = (w0 + off) - D * w0;
+                    acc_b = bfull * bfull;
+                    acc_r = r0 * r0;
+                    const uint32_t irow = ((uint32_t)(l - 1) * J.n3 + (uint32_t)(k - 1)) * J.n2 + (uint32_t)(j - 1);
+                    const uint32_t qf = irow * (uint32_t)J.half + m;
+                    const uint32_t ci = bctile(J, colour, qf);
+#pragma unroll
+                    for (int f = 0; f < 8; ++f) coef[ci + f * kTileSlots] = c[f];
+                    coef[ci + 8 * kTileSlots] = w0;
+                    const double inv = 1.0 / D;
+                    uint32_t hb[8];
+#pragma unroll
+                    for (int f = 0; f < 8; ++f) hb[f] = bf16_bits((float)(c[f] * inv));
+                    const u32x4 rec = {hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16), hb[4] | (hb[5] << 16),
+                                       hb[6] | (hb[7] << 16)};
+                    c16[(uint32_t)colour * (uint32_t)J.ntq * kTileSlots + qf] = rec;
                 }
-                double qs = 0.0;
-#pragma unroll
-                for (int f = 0; f < 8; ++f) qs += q[f];
-                const double scale = J.th2 * sqrt(J.eps2 + qs / 8.0);
-                double c[8];
-#pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    c[2 * d] = scale * J.G[(int64_t)d * J.npad + p - sd[d]] / sqrt(J.eps2 + q[2 * d]);
-                    c[2 * d + 1] = scale * J.G[(int64_t)d * J.npad + p] / sqrt(J.eps2 + q[2 * d + 1]);
-                }
-                double D = 1.0, bfull = w0, off = 0.0;
-#pragma unroll
-                for (int f = 0; f < 8; ++f) D += c[f];
-#pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    off += c[2 * d] * wm[d] + c[2 * d + 1] * wp[d];
-                    if (idx[d] == 1) bfull += c[2 * d] * wm[d];
-                    if (idx[d] == nn[d]) bfull += c[2 * d + 1] * wp[d];
-                }
-                const double r0 = (w0 + off) - D * w0;
-                acc_b = bfull * bfull;
-                acc_r = r0 * r0;
-                const int64_t irow = ((int64_t)(l - 1) * J.n3 + (k - 1)) * J.n2 + (j - 1);
-                const int64_t qf = irow * J.half + m;
-                const int64_t ci = bctile(J, colour, qf);
-#pragma unroll
-                for (int f = 0; f < 8; ++f) J.coef[ci + f * kTileSlots] = c[f];
-                J.coef[ci + 8 * kTileSlots] = w0;
-                const double inv = 1.0 / D;
-                uint32_t hb[8];
-#pragma unroll
-                for (int f = 0; f < 8; ++f) hb[f] = bf16_bits((float)(c[f] * inv));
-                J.c16[(int64_t)colour * J.ntq * kTileSlots + qf] =
-                    make_uint4(hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16), hb[4] | (hb[5] << 16), hb[6] | (hb[7] << 16));
+            }
+            const double bb = wave_sum(acc_b);
+            const double rr = wave_sum(acc_r);
+            if ((threadIdx.x & 63) == 0) {
+                pa[item * kWaves + (threadIdx.x >> 6)] = bb;
+                pb[item * kWaves + (threadIdx.x >> 6)] = rr;
             }
         }
-        const double bb = block_sum(acc_b, lds);
-        const double rr = block_sum(acc_r, lds);
-        if (threadIdx.x == 0) { J.part_a[item] = bb; J.part_b[item] = rr; }
-    }
+    });
 }
 
 // Per-job fixed-order reduction of the assembly partials (one block per job):
@@ -252,8 +307,8 @@ __global__ __launch_bounds__(kBlock) void kb_assemble_decide(BTable T)
     __shared__ double lds[4];
     for (int jb = blockIdx.x; jb < T.n_jobs; jb += gridDim.x) {
         const BJob& J = T.jobs[jb];
-        const double B2 = sum_partials(J.part_a, (int)J.nip, lds);
-        const double R2 = sum_partials(J.part_b, (int)J.nip, lds);
+        const double B2 = sum_partials(J.part_a, (int)(kWaves * J.nip), lds);
+        const double R2 = sum_partials(J.part_b, (int)(kWaves * J.nip), lds);
         if (threadIdx.x == 0) {
             Ctrl* C = J.C;
             C->bn = sqrt(B2);
@@ -267,43 +322,45 @@ __global__ __launch_bounds__(kBlock) void kb_assemble_decide(BTable T)
     }
 }
 
-// FP64 residual of x (both colours) for unfinished jobs; r/D to FP32; the
-// last item of each job applies its stopping rule.
+// FP64 residual of x (both colours) for unfinished jobs; r/D to FP32.
 __global__ __launch_bounds__(kBlock) void kb_residual(BTable T)
 {
-    __shared__ double lds[4];
-    for (ItemWalk it(T.both_start, T.n_jobs); it.next(); ++it.w) {
-        const int jb = it.jb;
-        const BJob& J = T.jobs[jb];
-        if (J.C->done) continue;
-        const int64_t item = it.w - T.both_start[jb];
-        const int colour = item >= J.nit ? 1 : 0;
-        const int64_t q = (item - colour * J.nit) * kItem + threadIdx.x;
-        double acc = 0.0;
-        int64_t r;
-        int m, j, k, l, par;
-        if (bdecode(J, colour, q, r, m, j, k, l, par)) {
-            const int64_t sy = J.rsu, sz = (int64_t)J.p2 * J.rsu, st = (int64_t)J.p2 * J.p3 * J.rsu;
-            const int64_t ui = bprow(J, j, k, l) * J.rsu + 1 + m;
-            const double* own = colour ? J.xb : J.xr;
-            const double* oth = colour ? J.xr : J.xb;
-            const double* cf = J.coef + bctile(J, colour, q);
-            const double c0 = cf[0], c1 = cf[kTileSlots], c2 = cf[2 * kTileSlots], c3 = cf[3 * kTileSlots];
-            const double c4 = cf[4 * kTileSlots], c5 = cf[5 * kTileSlots], c6 = cf[6 * kTileSlots];
-            const double c7 = cf[7 * kTileSlots];
-            double s = cf[8 * kTileSlots];
-            s += c0 * oth[ui - par] + c1 * oth[ui + 1 - par];
-            s += c2 * oth[ui - sy] + c3 * oth[ui + sy];
-            s += c4 * oth[ui - sz] + c5 * oth[ui + sz];
-            s += c6 * oth[ui - st] + c7 * oth[ui + st];
-            const double D = ((((((((1.0 + c0) + c1) + c2) + c3) + c4) + c5) + c6) + c7);
-            const double res = s - D * own[ui];
-            acc = res * res;
-            J.rf[(int64_t)colour * J.ntq * kTileSlots + q] = (float)(res / D);
+    for_runs(T.act_both, T.act_jobs, *T.n_act, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
+        const BJob J = T.jobs[jb];
+        const uint32_t sy = J.rsu, sz = (uint32_t)J.p2 * J.rsu, st = sz * (uint32_t)J.p3;
+        const uint32_t nit = (uint32_t)J.nit;
+        SS4_GLOBAL const double* xr = gbl(static_cast<const double*>(J.xr));
+        SS4_GLOBAL const double* xb = gbl(static_cast<const double*>(J.xb));
+        SS4_GLOBAL const double* coef = gbl(static_cast<const double*>(J.coef));
+        SS4_GLOBAL float* rf = gbl(J.rf);
+        SS4_GLOBAL double* pa = gbl(J.part_a);
+        for (uint32_t item = i0; item < i1; item += step) {
+            const int colour = item >= nit ? 1 : 0;
+            const uint32_t q = (item - (colour ? nit : 0u)) * kItem + threadIdx.x;
+            double acc = 0.0;
+            Cell c;
+            if (bdecode(J, colour, q, c)) {
+                const uint32_t ui = c.prow * J.rsu + 1 + c.m;
+                SS4_GLOBAL const double* own = colour ? xb : xr;
+                SS4_GLOBAL const double* oth = colour ? xr : xb;
+                SS4_GLOBAL const double* cf = coef + bctile(J, colour, q);
+                const double c0 = cf[0], c1 = cf[kTileSlots], c2 = cf[2 * kTileSlots], c3 = cf[3 * kTileSlots];
+                const double c4 = cf[4 * kTileSlots], c5 = cf[5 * kTileSlots], c6 = cf[6 * kTileSlots];
+                const double c7 = cf[7 * kTileSlots];
+                double s = cf[8 * kTileSlots];
+                s += c0 * oth[ui - c.par] + c1 * oth[ui + 1 - c.par];
+                s += c2 * oth[ui - sy] + c3 * oth[ui + sy];
+                s += c4 * oth[ui - sz] + c5 * oth[ui + sz];
+                s += c6 * oth[ui - st] + c7 * oth[ui + st];
+                const double D = ((((((((1.0 + c0) + c1) + c2) + c3) + c4) + c5) + c6) + c7);
+                const double res = s - D * own[ui];
+                acc = res * res;
+                rf[(uint32_t)colour * (uint32_t)J.ntq * kTileSlots + q] = (float)(res / D);
+            }
+            const double ws = wave_sum(acc);
+            if ((threadIdx.x & 63) == 0) pa[item * kWaves + (threadIdx.x >> 6)] = ws;
         }
-        const double bs = block_sum(acc, lds);
-        if (threadIdx.x == 0) J.part_a[item] = bs;
-    }
+    });
 }
 
 // Per-job fixed-order reduction of the residual partials and the refinement
@@ -312,10 +369,10 @@ __global__ __launch_bounds__(kBlock) void kb_residual_decide(BTable T)
 {
     __shared__ double lds[4];
     const int pass = *T.pass;
-    for (int jb = blockIdx.x; jb < T.n_jobs; jb += gridDim.x) {
-        const BJob& J = T.jobs[jb];
-        if (J.C->done) continue;
-        const double R2 = sum_partials(J.part_a, (int)(2 * J.nit), lds);
+    const int na = *T.n_act;
+    for (int a = blockIdx.x; a < na; a += gridDim.x) {
+        const BJob& J = T.jobs[T.act_jobs[a]];
+        const double R2 = sum_partials(J.part_a, (int)(kWaves * 2 * J.nit), lds);
         if (threadIdx.x == 0) {
             Ctrl* C = J.C;
             const double R = sqrt(R2);
@@ -335,47 +392,90 @@ template <int COLOR>
 __global__ __launch_bounds__(kBlock) void kb_sweep(BTable T)
 {
     const float om = T.omega, om1 = 1.0f - T.omega;
-    for (ItemWalk it(T.col_start, T.n_jobs); it.next(); ++it.w) {
-        const int jb = it.jb;
-        const BJob& J = T.jobs[jb];
-        if (J.C->done) continue;
-        const int64_t q = (it.w - T.col_start[jb]) * kItem + threadIdx.x;
-        int64_t r;
-        int m, j, k, l, par;
-        if (!bdecode(J, COLOR, q, r, m, j, k, l, par)) continue;
-        const int64_t sy = J.rsu, sz = (int64_t)J.p2 * J.rsu, st = (int64_t)J.p2 * J.p3 * J.rsu;
-        const int64_t ui = bprow(J, j, k, l) * J.rsu + 1 + m;
-        float* own = COLOR ? J.db : J.dr;
-        const float* oth = COLOR ? J.dr : J.db;
-        const int64_t qi = (int64_t)COLOR * J.ntq * kTileSlots + q;
-        const uint4 cw = J.c16[qi];
-        float s = J.rf[qi];
-        s += bf16_lo(cw.x) * oth[ui - par] + bf16_hi(cw.x) * oth[ui + 1 - par];
-        s += bf16_lo(cw.y) * oth[ui - sy] + bf16_hi(cw.y) * oth[ui + sy];
-        s += bf16_lo(cw.z) * oth[ui - sz] + bf16_hi(cw.z) * oth[ui + sz];
-        s += bf16_lo(cw.w) * oth[ui - st] + bf16_hi(cw.w) * oth[ui + st];
-        own[ui] = om * s + om1 * own[ui];
-    }
+    for_runs(T.act_col, T.act_jobs, *T.n_act, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
+        const BJob J = T.jobs[jb];
+        const uint32_t sy = J.rsu, sz = (uint32_t)J.p2 * J.rsu, st = sz * (uint32_t)J.p3;
+        SS4_GLOBAL float* own = gbl(COLOR ? J.db : J.dr);
+        SS4_GLOBAL const float* oth = gbl(static_cast<const float*>(COLOR ? J.dr : J.db));
+        const uint32_t cb = (uint32_t)COLOR * (uint32_t)J.ntq * kTileSlots;
+        SS4_GLOBAL const u32x4* c16 = gbl(reinterpret_cast<const u32x4*>(J.c16));
+        SS4_GLOBAL const float* rf = gbl(static_cast<const float*>(J.rf));
+        for (uint32_t item = i0; item < i1; item += step) {
+            const uint32_t q = item * kItem + threadIdx.x;
+            Cell c;
+            if (!bdecode(J, COLOR, q, c)) continue;
+            const uint32_t ui = c.prow * J.rsu + 1 + c.m;
+            const u32x4 cw = c16[cb + q];
+            float s = rf[cb + q];
+            s += bf16_lo(cw.x) * oth[ui - c.par] + bf16_hi(cw.x) * oth[ui + 1 - c.par];
+            s += bf16_lo(cw.y) * oth[ui - sy] + bf16_hi(cw.y) * oth[ui + sy];
+            s += bf16_lo(cw.z) * oth[ui - sz] + bf16_hi(cw.z) * oth[ui + sz];
+            s += bf16_lo(cw.w) * oth[ui - st] + bf16_hi(cw.w) * oth[ui + st];
+            own[ui] = om * s + om1 * own[ui];
+        }
+    });
 }
 
-// x += d, d = 0 for unfinished jobs; the last block advances the pass counter.
+// x += d, d = 0 for unfinished jobs.
 __global__ __launch_bounds__(kBlock) void kb_update(BTable T)
 {
-    for (ItemWalk it(T.both_start, T.n_jobs); it.next(); ++it.w) {
-        const int jb = it.jb;
-        const BJob& J = T.jobs[jb];
-        if (J.C->done) continue;
-        const int64_t item = it.w - T.both_start[jb];
-        const int colour = item >= J.nit ? 1 : 0;
-        const int64_t q = (item - colour * J.nit) * kItem + threadIdx.x;
-        int64_t r;
-        int m, j, k, l, par;
-        if (!bdecode(J, colour, q, r, m, j, k, l, par)) continue;
-        const int64_t ui = bprow(J, j, k, l) * J.rsu + 1 + m;
-        double* x = colour ? J.xb : J.xr;
-        float* d = colour ? J.db : J.dr;
-        x[ui] += (double)d[ui];
-        d[ui] = 0.0f;
+    for_runs(T.act_both, T.act_jobs, *T.n_act, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
+        const BJob J = T.jobs[jb];
+        const uint32_t nit = (uint32_t)J.nit;
+        for (uint32_t item = i0; item < i1; item += step) {
+            const int colour = item >= nit ? 1 : 0;
+            const uint32_t q = (item - (colour ? nit : 0u)) * kItem + threadIdx.x;
+            Cell c;
+            if (!bdecode(J, colour, q, c)) continue;
+            const uint32_t ui = c.prow * J.rsu + 1 + c.m;
+            SS4_GLOBAL double* x = gbl(colour ? J.xb : J.xr);
+            SS4_GLOBAL float* d = gbl(colour ? J.db : J.dr);
+            x[ui] += (double)d[ui];
+            d[ui] = 0.0f;
+        }
+    });
+}
+
+// Compacted list of unfinished jobs and its item prefixes (one block; a
+// fixed-order scan, so the list is in job order).
+constexpr int kScan = 1024;
+__global__ __launch_bounds__(kScan) void kb_compact(BTable T)
+{
+    __shared__ int s_cnt[kScan];
+    __shared__ int64_t s_sum[kScan];
+    const int per = (T.n_jobs + kScan - 1) / kScan;
+    const int lo = threadIdx.x * per;
+    const int hi = lo + per < T.n_jobs ? lo + per : T.n_jobs;
+    int cnt = 0;
+    int64_t sum = 0;
+    for (int jb = lo; jb < hi; ++jb)
+        if (!T.jobs[jb].C->done) { ++cnt; sum += T.jobs[jb].nit; }
+    s_cnt[threadIdx.x] = cnt;
+    s_sum[threadIdx.x] = sum;
+    __syncthreads();
+    for (int d = 1; d < kScan; d <<= 1) {            // inclusive Hillis-Steele scan
+        const int c = threadIdx.x >= d ? s_cnt[threadIdx.x - d] : 0;
+        const int64_t v = threadIdx.x >= d ? s_sum[threadIdx.x - d] : 0;
+        __syncthreads();
+        s_cnt[threadIdx.x] += c;
+        s_sum[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int pos = s_cnt[threadIdx.x] - cnt;
+    int64_t base = s_sum[threadIdx.x] - sum;
+    for (int jb = lo; jb < hi; ++jb) {
+        if (T.jobs[jb].C->done) continue;
+        T.act_jobs[pos] = jb;
+        T.act_col[pos] = base;
+        T.act_both[pos] = 2 * base;
+        ++pos;
+        base += T.jobs[jb].nit;
+    }
+    if (threadIdx.x == kScan - 1) {
+        const int na = s_cnt[kScan - 1];
+        T.act_col[na] = s_sum[kScan - 1];
+        T.act_both[na] = 2 * s_sum[kScan - 1];
+        *T.n_act = na;
     }
 }
 
@@ -406,19 +506,20 @@ __global__ void kb_zero_d(BTable T)
 // x -> interior of the padded u, every job
 __global__ __launch_bounds__(kBlock) void kb_unsplit(BTable T)
 {
-    for (ItemWalk it(T.both_start, T.n_jobs); it.next(); ++it.w) {
-        const int jb = it.jb;
-        const BJob& J = T.jobs[jb];
-        const int64_t item = it.w - T.both_start[jb];
-        const int colour = item >= J.nit ? 1 : 0;
-        const int64_t q = (item - colour * J.nit) * kItem + threadIdx.x;
-        int64_t r;
-        int m, j, k, l, par;
-        if (!bdecode(J, colour, q, r, m, j, k, l, par)) continue;
-        const int i = 2 * m + 2 - (par ? 1 : 0);
-        const int64_t prow = bprow(J, j, k, l);
-        J.u[prow * J.p1 + i] = (colour ? J.xb : J.xr)[prow * J.rsu + 1 + m];
-    }
+    for_runs(T.both_start, nullptr, T.n_jobs, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
+        const BJob J = T.jobs[jb];
+        const uint32_t nit = (uint32_t)J.nit;
+        SS4_GLOBAL double* u = gbl(J.u);
+        for (uint32_t item = i0; item < i1; item += step) {
+            const int colour = item >= nit ? 1 : 0;
+            const uint32_t q = (item - (colour ? nit : 0u)) * kItem + threadIdx.x;
+            Cell c;
+            if (!bdecode(J, colour, q, c)) continue;
+            const int i = 2 * c.m + 2 - (c.par ? 1 : 0);
+            SS4_GLOBAL const double* x = gbl(static_cast<const double*>(colour ? J.xb : J.xr));
+            u[c.prow * (uint32_t)J.p1 + i] = x[c.prow * J.rsu + 1 + c.m];
+        }
+    });
 }
 
 // local rescaling of every job: one block per ball (global ball list)
@@ -508,7 +609,8 @@ bool plan_batch_job(const int32_t n[4], int32_t nc, BJob* J, size_t* bytes)
 {
     for (int d = 0; d < 4; ++d)
         if (n[d] < 1 || n[d] > (1 << 16)) return false;
-    if ((int64_t)(n[0] + 2) * (n[1] + 2) * (n[2] + 2) * (n[3] + 2) >= ((int64_t)1 << 31)) return false;
+    // windows: every per-job array stays below 4 GiB (32-bit byte offsets)
+    if ((int64_t)(n[0] + 2) * (n[1] + 2) * (n[2] + 2) * (n[3] + 2) > kBatchMaxPadded) return false;
     BJob b{};
     b.n1 = n[0]; b.n2 = n[1]; b.n3 = n[2]; b.n4 = n[3];
     b.p1 = n[0] + 2; b.p2 = n[1] + 2; b.p3 = n[2] + 2; b.p4 = n[3] + 2;
@@ -522,8 +624,15 @@ bool plan_batch_job(const int32_t n[4], int32_t nc, BJob* J, size_t* bytes)
     b.ncq = b.nrow_int * b.half;
     b.ntq = (b.ncq + kTileSlots - 1) / kTileSlots;
     b.nip = (b.npad + kItem - 1) / kItem;
+    auto magic = [](uint32_t d) { return (((uint64_t)1 << 63) + d - 1) / d; };
+    b.mg_half = magic((uint32_t)b.half);
+    b.mg_n2 = magic((uint32_t)n[1]);
+    b.mg_n3 = magic((uint32_t)n[2]);
+    b.mg_p1 = magic((uint32_t)b.p1);
+    b.mg_p2 = magic((uint32_t)b.p2);
+    b.mg_p3 = magic((uint32_t)b.p3);
     b.nit = (b.ncq + kItem - 1) / kItem;
-    const int64_t parts = b.nip > 2 * b.nit ? b.nip : 2 * b.nit;
+    const int64_t parts = kWaves * (b.nip > 2 * b.nit ? b.nip : 2 * b.nit);
     size_t off = 0;
     auto take = [&](size_t nbytes) { const size_t o = off; off += al256(nbytes); return o; };
     const size_t o_ctrl = take(sizeof(Ctrl));
@@ -564,7 +673,8 @@ size_t batch_job_bytes(const int32_t n[4], int32_t nc)
 size_t batch_table_bytes(int32_t n_jobs)
 {
     const size_t nj = (size_t)(n_jobs > 0 ? n_jobs : 1);
-    return al256(sizeof(BJob) * nj) + al256(sizeof(Ctrl) * nj) + 4 * al256(sizeof(int64_t) * (nj + 1)) + 256;
+    return al256(sizeof(BJob) * nj) + al256(sizeof(Ctrl) * nj) + 6 * al256(sizeof(int64_t) * (nj + 1)) +
+           al256(sizeof(int) * nj) + 256;
 }
 
 namespace {
@@ -680,8 +790,12 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
     T.col_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
     T.both_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
     T.ball_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
+    T.act_col = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
+    T.act_both = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
+    T.act_jobs = reinterpret_cast<int*>(tb + off); off += al256(sizeof(int) * n_jobs);
     T.active = reinterpret_cast<int*>(tb + off);
     T.pass = T.active + 1;
+    T.n_act = T.active + 2;
     T.n_jobs = n_jobs;
     const int m = sp.inner_sweeps;
     T.max_outer = sp.max_iter / m > 1 ? sp.max_iter / m : 1;
@@ -701,6 +815,7 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
     const int g_dec = n_jobs < 4096 ? n_jobs : 4096;
     kb_assemble<<<g_asm, kBlock, 0, s>>>(T);
     kb_assemble_decide<<<g_dec, kBlock, 0, s>>>(T);
+    kb_compact<<<1, kScan, 0, s>>>(T);
     kb_zero_d<<<g_zero, 256, 0, s>>>(T);
     SS4_LAUNCHED("batched: assemble");
 
@@ -754,6 +869,7 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
     auto enqueue_pass = [&]() {
         kb_residual<<<g_res, kBlock, 0, s>>>(T);
         kb_residual_decide<<<g_dec, kBlock, 0, s>>>(T);
+        kb_compact<<<1, kScan, 0, s>>>(T);
         for (int it = 0; it < m; ++it) {
             kb_sweep<0><<<g_sw, kBlock, 0, s>>>(T);
             kb_sweep<1><<<g_sw, kBlock, 0, s>>>(T);
