@@ -445,90 +445,6 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tm(SweepArgs a)
     finish_sweep<COLOR>(a, acc, lds, &flag);
 }
 
-// Frame-marching half-sweep as k_sweep_tm, with wave-uniform addressing: a
-// wave's row of u and its coefficient tile start at addresses held in scalar
-// registers, and a lane adds only its slot.  Same arithmetic, same order.
-// ORDER 0: column tiles dealt k-fastest; 1: slot-tile fastest, then k.
-template <int COLOR, int ORDER>
-__global__ __launch_bounds__(kBlock) void k_sweep_tu(SweepArgs a)
-{
-    __shared__ double lds[4];
-    __shared__ int flag;
-    Ctrl* C = a.C;
-    if (C->done) return;
-    const Layout& L = a.L;
-    const int tx = threadIdx.x & 63;
-    const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int ntm = (L.half + 63) >> 6;                // 64-slot column tiles per row
-    const int njb = (L.n2 + 3) >> 2;
-    const int64_t ncol = (int64_t)ntm * njb * L.n3;
-    const int64_t sy = L.rs, sz = (int64_t)L.p2 * L.rs, st = (int64_t)L.p2 * L.p3 * L.rs;
-    const int64_t cst = (int64_t)L.n2 * L.n3 * L.ntm * kTileVals;   // coefficient stride between frames
-    const int last_slot = L.n1 >> 1;
-    const double om = a.omega, om1 = 1.0 - a.omega;
-    double acc = 0.0;
-    for (TileWalk tw(ncol); tw.t < tw.end; tw.t += tw.step) {
-        int k, jb, mt;
-        if (ORDER == 0) {
-            k = (int)(tw.t % L.n3) + 1;
-            const int64_t t2 = tw.t / L.n3;
-            jb = (int)(t2 % njb);
-            mt = (int)(t2 / njb);
-        } else {
-            mt = (int)(tw.t % ntm);
-            const int64_t t2 = tw.t / ntm;
-            k = (int)(t2 % L.n3) + 1;
-            jb = (int)(t2 / L.n3);
-        }
-        const int j = jb * 4 + ty + 1;
-        if (j > L.n2) continue;                            // whole wave
-        const int m0 = mt * 64;
-        const int m = m0 + tx;
-        const bool sok = m <= last_slot;
-        const int64_t rb = ((int64_t)k * L.p2 + j) * L.rs + L.xoff + m0;   // row (j,k,l=0), slot m0
-        const double* __restrict__ uo = a.uoth + rb;
-        const double* __restrict__ ui0 = a.uin + rb;
-        double* uw0 = a.uout + rb;
-        const double* __restrict__ c0p = a.coef + ctile(L, COLOR, ((int64_t)(k - 1) * L.n2 + (j - 1)), m0);
-        double Bm = sok ? uo[tx] : 0.0;
-        double Bc = sok ? uo[st + tx] : 0.0;
-        for (int l = 1; l <= L.n4; ++l) {
-            const double* ur = uo + (int64_t)l * st;
-            const double Bp = sok ? ur[st + tx] : 0.0;
-            const int par = (COLOR + j + k + l) & 1;
-            double left = __shfl_up(Bc, 1);
-            double right = __shfl_down(Bc, 1);
-            if (tx == 0 && par) left = ur[-1];
-            if (tx == 63 && !par && m + 1 <= last_slot) right = ur[64];
-            const int cnt = par ? (L.n1 + 1) >> 1 : L.n1 >> 1;
-            if (m < cnt) {
-                const double* cf = c0p + (int64_t)(l - 1) * cst + tx;
-                const double c0 = ld_stream(cf), c1 = ld_stream(cf + kTileSlots);
-                const double c2 = ld_stream(cf + 2 * kTileSlots), c3 = ld_stream(cf + 3 * kTileSlots);
-                const double c4 = ld_stream(cf + 4 * kTileSlots), c5 = ld_stream(cf + 5 * kTileSlots);
-                const double c6 = ld_stream(cf + 6 * kTileSlots), c7 = ld_stream(cf + 7 * kTileSlots);
-                const double xl = par ? left : Bc;
-                const double xr = par ? Bc : right;
-                double s = ld_stream(cf + 8 * kTileSlots);
-                s += c0 * xl + c1 * xr;
-                s += c2 * ur[tx - sy] + c3 * ur[tx + sy];
-                s += c4 * ur[tx - sz] + c5 * ur[tx + sz];
-                s += c6 * Bm + c7 * Bp;
-                const double D = ((((((((1.0 + c0) + c1) + c2) + c3) + c4) + c5) + c6) + c7);
-                const double ubar = s / D;
-                const int64_t lo = (int64_t)l * st + tx;
-                const double uold = ld_stream(ui0 + lo);
-                st_stream(uw0 + lo, om * ubar + om1 * uold);
-                const double rres = COLOR == 0 ? D * (ubar - uold) : D * om1 * (ubar - uold);
-                acc += rres * rres;
-            }
-            Bm = Bc;
-            Bc = Bp;
-        }
-    }
-    finish_sweep<COLOR>(a, acc, lds, &flag);
-}
-
 // Half-sweep, frame-marching with two cells per lane (rows of >= 64 slots,
 // whose u rows are 128-byte aligned): a wave covers one 128-slot coefficient
 // tile of one row, lane t owns slots m = 2t, 2t+1, and every stream moves 16
@@ -660,10 +576,9 @@ int sweep_grid(const Layout& L, int variant)
         const int64_t ncol = (int64_t)L.ntm * ((L.n2 + 3) >> 2) * L.n3;
         return (int)((ncol + kXcd - 1) / kXcd * kXcd);
     }
-    if (variant == 1 || variant == 3 || variant == 4) {
+    if (variant == 1) {
         work = (int64_t)L.ntm * ((L.n2 + 3) >> 2) * L.n3;
-        res = resident_grid(variant >= 3 ? reinterpret_cast<const void*>(&k_sweep_tu<0, 0>)
-                                         : reinterpret_cast<const void*>(&k_sweep_tm<0>));
+        res = resident_grid(reinterpret_cast<const void*>(&k_sweep_tm<0>));
     } else {
         work = (int64_t)L.ntm * ((L.nrow_int + 3) >> 2);
         res = resident_grid(reinterpret_cast<const void*>(&k_sweep<0>));
@@ -682,8 +597,6 @@ int sweep_variant(const Layout& L)
     static const char* env = getenv("SUBSURF4D_SWEEP");
     if (env && env[0] == 'r') return 0;
     if (env && env[0] == 'p' && wide) return 2;
-    if (env && env[0] == 'u') return 3;
-    if (env && env[0] == 'v') return 4;
     return 1;
 }
 
@@ -749,16 +662,12 @@ int run_sor_loop(const WsPlan& P, const subsurf4d_step_params& sp, void* ws, hip
             red.uout = ured[k & 1];
             red.check = (k >= 2) && (((k - 1) % check_every == 0) || (k - 1 >= max_iter));
             if (variant == 2) k_sweep_t2<0><<<grid, kBlock, 0, s>>>(red);
-            else if (variant == 3) k_sweep_tu<0, 0><<<grid, kBlock, 0, s>>>(red);
-            else if (variant == 4) k_sweep_tu<0, 1><<<grid, kBlock, 0, s>>>(red);
             else if (variant == 1) k_sweep_tm<0><<<grid, kBlock, 0, s>>>(red);
             else k_sweep<0><<<grid, kBlock, 0, s>>>(red);
             if (k <= max_iter) {
                 black.k = k;
                 black.uoth = ured[k & 1];
                 if (variant == 2) k_sweep_t2<1><<<grid, kBlock, 0, s>>>(black);
-                else if (variant == 3) k_sweep_tu<1, 0><<<grid, kBlock, 0, s>>>(black);
-                else if (variant == 4) k_sweep_tu<1, 1><<<grid, kBlock, 0, s>>>(black);
                 else if (variant == 1) k_sweep_tm<1><<<grid, kBlock, 0, s>>>(black);
                 else k_sweep<1><<<grid, kBlock, 0, s>>>(black);
             }
