@@ -276,6 +276,44 @@ size_t subsurf4d_batch_table_bytes(int32_t n_jobs);
 int subsurf4d_step_batched(const subsurf4d_batch_job* jobs, int32_t n_jobs, const subsurf4d_step_params* params,
                            subsurf4d_result* results, void* table, size_t table_bytes, void* stream);
 
+/*
+ * Batched preparation of many windows (A1-A3 of the per-job preparation, then
+ * the initial function and its local rescale: the implementation overview of
+ * Sec. 3.5 up to the first time step), for jobs that will be advanced with
+ * subsurf4d_step_batched.  Every job gets what subsurf4d_prepare_g,
+ * subsurf4d_init_u (v, R) and subsurf4d_rescale (ball_r; skipped if
+ * ball_r < 0) compute for it: owner map and G on the job's arrays, u0 rescaled
+ * in u.  Each job's two presmoothing solves keep their own stopping rule.
+ * All jobs of a call must share h.
+ */
+typedef struct {
+    subsurf4d_grid grid;
+    const void* image;                /* device, interior, x fastest, dtype image_dtype */
+    int32_t image_dtype;              /* subsurf4d_dtype */
+    int32_t n_centres;
+    const subsurf4d_centre* centres;  /* device: ball centres (thresholding and rescale) */
+    int32_t n_seeds;
+    int32_t reserved;
+    const subsurf4d_centre* seeds;    /* device: seeds of the initial function */
+    double* G;                        /* device, out: 4 x padded */
+    int32_t* owner;                   /* device, out: interior */
+    double* u;                        /* device, out: padded u0 after the rescale */
+    void* workspace;                  /* device: the job's batched-step workspace, used as scratch */
+    size_t workspace_bytes;           /* >= subsurf4d_batch_workspace_bytes(grid, n_centres) */
+} subsurf4d_batch_prepare_job;
+
+/*
+ * Prepare every job.  jobs (host array of n_jobs), params as for
+ * subsurf4d_prepare_g, statuses (host array of n_jobs, may be NULL: per job 0,
+ * SUBSURF4D_NOT_CONVERGED if a presmoothing solve hit smooth_max_iter, or
+ * SUBSURF4D_ENONFINITE), table (device, >= subsurf4d_batch_table_bytes(n_jobs),
+ * 256-byte aligned).  Synchronises `stream`.  Returns 0,
+ * SUBSURF4D_NOT_CONVERGED if any job's solve hit its cap, or a negative code.
+ */
+int subsurf4d_prepare_batched(const subsurf4d_batch_prepare_job* jobs, int32_t n_jobs,
+                              const subsurf4d_prepare_params* params, double v, double R, double ball_r,
+                              int32_t* statuses, void* table, size_t table_bytes, void* stream);
+
 /* Static text for a status code. */
 const char* subsurf4d_status_string(int status);
 

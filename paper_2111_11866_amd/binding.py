@@ -28,7 +28,7 @@ EXPORTED = (
     "subsurf4d_assemble", "subsurf4d_step", "subsurf4d_solve", "subsurf4d_status_string",
     "subsurf4d_last_error", "subsurf4d_version", "subsurf4d_timing", "subsurf4d_copy_probe",
     "subsurf4d_batch_workspace_bytes", "subsurf4d_batch_table_bytes", "subsurf4d_step_batched",
-    "subsurf4d_prepare_workspace_bytes",
+    "subsurf4d_prepare_workspace_bytes", "subsurf4d_prepare_batched",
 )
 
 
@@ -59,6 +59,14 @@ class BatchJobC(ctypes.Structure):
     _fields_ = [("grid", Grid), ("G", ctypes.c_void_p), ("u", ctypes.c_void_p), ("owner", ctypes.c_void_p),
                 ("centres", ctypes.c_void_p), ("n_centres", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+
+
+class BatchPrepareJobC(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("image", ctypes.c_void_p), ("image_dtype", ctypes.c_int32),
+                ("n_centres", ctypes.c_int32), ("centres", ctypes.c_void_p), ("n_seeds", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("seeds", ctypes.c_void_p), ("G", ctypes.c_void_p),
+                ("owner", ctypes.c_void_p), ("u", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
 
 
 class Result(ctypes.Structure):
@@ -157,6 +165,9 @@ def lib():
         L.subsurf4d_batch_table_bytes.restype = SZ
         L.subsurf4d_step_batched.argtypes = [ctypes.POINTER(BatchJobC), I, ctypes.POINTER(StepParamsC),
                                              ctypes.POINTER(Result), P, SZ, P]
+        L.subsurf4d_prepare_batched.argtypes = [ctypes.POINTER(BatchPrepareJobC), I,
+                                                ctypes.POINTER(PrepareParamsC), D, D, D,
+                                                ctypes.POINTER(ctypes.c_int32), P, SZ, P]
         _lib = L
     return _lib
 
@@ -301,6 +312,22 @@ def step_batched(jobs, params: StepParams, table, stream=None):
     return rc, [r.as_dict() for r in res]
 
 
+def prepare_batched(jobs, pp: PrepareParams, v, R, ball_r, table, stream=None):
+    """Batched preparation (owner map, G, u0 rescaled) of Job objects created
+    with batch=True.  Returns (status, per-job statuses)."""
+    import torch
+
+    arr = (BatchPrepareJobC * len(jobs))()
+    for q, j in enumerate(jobs):
+        dt = {torch.uint8: U8, torch.float32: F32, torch.float64: F64}[j.image.dtype]
+        arr[q] = BatchPrepareJobC(grid(j.n, j.h), _p(j.image), dt, int(j.nc), _p(j.centres), int(j.ns), 0,
+                                  _p(j.seeds), _p(j.G), _p(j.owner), _p(j.u), _p(j.bws), j.bws.numel())
+    st = (ctypes.c_int32 * len(jobs))()
+    rc = _check(lib().subsurf4d_prepare_batched(arr, len(jobs), ctypes.byref(pp.c()), float(v), float(R),
+                                                 float(ball_r), st, _p(table), table.numel(), _stream(stream)))
+    return rc, list(st)
+
+
 def version() -> str:
     return lib().subsurf4d_version().decode()
 
@@ -321,9 +348,13 @@ class Job:
         self.G = torch.empty((4,) + padded_shape(self.n), dtype=torch.float64, device=device)
         self.owner = torch.empty(interior_shape(self.n), dtype=torch.int32, device=device)
         self.u = torch.empty(padded_shape(self.n), dtype=torch.float64, device=device)
-        # full single-job workspace, or a caller-shared one (e.g. one preparation
-        # workspace reused by many batched windows)
-        self.ws = shared_ws if shared_ws is not None else alloc_workspace(self.n, self.nc, precision, device)
+        # full single-job workspace, a caller-shared one (e.g. one preparation
+        # workspace reused by many batched windows), or none (shared_ws=False:
+        # a batched job prepared with prepare_batched)
+        if shared_ws is False:
+            self.ws = None
+        else:
+            self.ws = shared_ws if shared_ws is not None else alloc_workspace(self.n, self.nc, precision, device)
         self.bws = None
         if batch:
             import torch

@@ -117,6 +117,7 @@ static_assert(sizeof(subsurf4d_prepare_params) == 80, "prepare params layout");
 static_assert(sizeof(subsurf4d_step_params) == 80, "step params layout");
 static_assert(sizeof(subsurf4d_result) == 32, "result layout");
 static_assert(sizeof(subsurf4d_batch_job) == 80, "batch job layout");
+static_assert(sizeof(subsurf4d_batch_prepare_job) == 104, "batch prepare job layout");
 
 namespace {
 
@@ -201,6 +202,25 @@ size_t subsurf4d_prepare_workspace_bytes(const subsurf4d_grid* grid, int32_t n_c
     }
 }
 
+namespace {
+
+int check_prepare_params(const subsurf4d_prepare_params* params)
+{
+    if (!params) return fail(SUBSURF4D_EINVAL, "NULL argument");
+    const subsurf4d_prepare_params& p = *params;
+    if (!(p.K >= 0.0) || !std::isfinite(p.K)) return fail(SUBSURF4D_EINVAL, "K must be >= 0");
+    if (!(p.lambda >= 0.0 && p.lambda <= 1.0)) return fail(SUBSURF4D_EINVAL, "lambda must be in [0,1]");
+    if (!(p.ball_r >= 0.0 && p.ball_r <= 1e6)) return fail(SUBSURF4D_EINVAL, "ball_r out of range");
+    if (!(p.smooth_tau >= 0.0) || p.smooth_steps < 0) return fail(SUBSURF4D_EINVAL, "bad smoothing parameters");
+    if (p.smooth_steps > 0 && (!(p.smooth_omega < 2.0) || p.smooth_max_iter < 1 ||
+                               !(p.smooth_tol >= 0.0)))
+        return fail(SUBSURF4D_EINVAL, "bad smoothing solver parameters");
+    if (!std::isfinite(p.image_scale)) return fail(SUBSURF4D_EINVAL, "image_scale must be finite");
+    return 0;
+}
+
+}  // namespace
+
 int subsurf4d_prepare_g(const subsurf4d_grid* grid, const void* image, int32_t image_dtype,
                         const subsurf4d_centre* centres, int32_t n_centres,
                         const subsurf4d_prepare_params* params, double* G, int32_t* owner, void* workspace,
@@ -213,15 +233,8 @@ int subsurf4d_prepare_g(const subsurf4d_grid* grid, const void* image, int32_t i
     if (n_centres < 0 || (n_centres > 0 && !centres)) return fail(SUBSURF4D_EINVAL, "bad centres");
     if (image_dtype != SUBSURF4D_U8 && image_dtype != SUBSURF4D_F32 && image_dtype != SUBSURF4D_F64)
         return fail(SUBSURF4D_EINVAL, "unknown image dtype");
+    if (int rc = check_prepare_params(params)) return rc;
     const subsurf4d_prepare_params& p = *params;
-    if (!(p.K >= 0.0) || !std::isfinite(p.K)) return fail(SUBSURF4D_EINVAL, "K must be >= 0");
-    if (!(p.lambda >= 0.0 && p.lambda <= 1.0)) return fail(SUBSURF4D_EINVAL, "lambda must be in [0,1]");
-    if (!(p.ball_r >= 0.0 && p.ball_r <= 1e6)) return fail(SUBSURF4D_EINVAL, "ball_r out of range");
-    if (!(p.smooth_tau >= 0.0) || p.smooth_steps < 0) return fail(SUBSURF4D_EINVAL, "bad smoothing parameters");
-    if (p.smooth_steps > 0 && (!(p.smooth_omega < 2.0) || p.smooth_max_iter < 1 ||
-                               !(p.smooth_tol >= 0.0)))
-        return fail(SUBSURF4D_EINVAL, "bad smoothing solver parameters");
-    if (!std::isfinite(p.image_scale)) return fail(SUBSURF4D_EINVAL, "image_scale must be finite");
     WsPlan P;
     if (!plan_workspace(grid->n, n_centres, SUBSURF4D_FP64, &P)) return fail(SUBSURF4D_ESHAPE, "grid too large");
     if (int rc = check_ws(P, workspace, workspace_bytes, P.big + P.prep_bytes)) return rc;
@@ -362,6 +375,35 @@ int subsurf4d_step_batched(const subsurf4d_batch_job* jobs, int32_t n_jobs, cons
             return fail(SUBSURF4D_EINVAL, "rescale needs centres and owner");
     }
     return run_batch_step(jobs, n_jobs, *params, results, table, table_bytes, static_cast<hipStream_t>(stream));
+    SS4_GUARD_END
+}
+
+int subsurf4d_prepare_batched(const subsurf4d_batch_prepare_job* jobs, int32_t n_jobs,
+                              const subsurf4d_prepare_params* params, double v, double R, double ball_r,
+                              int32_t* statuses, void* table, size_t table_bytes, void* stream)
+{
+    SS4_GUARD_BEGIN
+    g_error.clear();
+    if (!jobs || n_jobs < 1 || !table) return fail(SUBSURF4D_EINVAL, "bad batch arguments");
+    if (int rc = check_prepare_params(params)) return rc;
+    if (!(v > 0.0) || !std::isfinite(v)) return fail(SUBSURF4D_EINVAL, "v must be positive");
+    if (!std::isfinite(R) || R > 1e6) return fail(SUBSURF4D_EINVAL, "R out of range");
+    if (!std::isfinite(ball_r) || ball_r > 1e6) return fail(SUBSURF4D_EINVAL, "ball_r out of range");
+    if (reinterpret_cast<uintptr_t>(table) % 256 != 0) return fail(SUBSURF4D_EINVAL, "table must be 256-byte aligned");
+    for (int q = 0; q < n_jobs; ++q) {
+        const subsurf4d_batch_prepare_job& j = jobs[q];
+        if (int rc = check_grid(&j.grid)) return rc;
+        if (!j.image || !j.G || !j.owner || !j.u || !j.workspace)
+            return fail(SUBSURF4D_EINVAL, "batch job with a NULL pointer");
+        if (j.image_dtype != SUBSURF4D_U8 && j.image_dtype != SUBSURF4D_F32 && j.image_dtype != SUBSURF4D_F64)
+            return fail(SUBSURF4D_EINVAL, "unknown image dtype");
+        if (j.n_centres < 0 || (j.n_centres > 0 && !j.centres)) return fail(SUBSURF4D_EINVAL, "bad centres");
+        if (j.n_seeds < 0 || (j.n_seeds > 0 && !j.seeds)) return fail(SUBSURF4D_EINVAL, "bad seeds");
+        if (reinterpret_cast<uintptr_t>(j.workspace) % 256 != 0)
+            return fail(SUBSURF4D_EINVAL, "job workspace must be 256-byte aligned");
+    }
+    return run_batch_prepare(jobs, n_jobs, *params, v, R, ball_r, statuses, table, table_bytes,
+                             static_cast<hipStream_t>(stream));
     SS4_GUARD_END
 }
 

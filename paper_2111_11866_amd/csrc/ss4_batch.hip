@@ -24,155 +24,11 @@
 #include <mutex>
 #include <vector>
 
-#include "ss4_internal.hpp"
+#include "ss4_batch.hpp"
 
 namespace ss4 {
 
-struct BJob {
-    int n1, n2, n3, n4, p1, p2, p3, p4;
-    int half, rsu, nc, pad0;
-    int64_t nrow_int, nrow_pad, npad, nint;
-    int64_t ncq;          // flat cells of one colour (incl. inactive slots)
-    int64_t ntq;          // 128-tiles of one colour
-    int64_t nip, nit;     // items over padded cells / over one colour
-    uint64_t mg_half, mg_n2, mg_n3, mg_p1, mg_p2, mg_p3;   // ceil(2^63 / d) for the index divisions
-    double th2, eps2, inv_h;
-    const double* G;
-    double* u;
-    const int32_t* owner;
-    const subsurf4d_centre* centres;
-    double* xr;
-    double* xb;
-    double* coef;
-    uint4* c16;
-    float* rf;
-    float* dr;
-    float* db;
-    double* part_a;       // per-wave partials (>= kWaves * max(nip, 2*nit))
-    double* part_b;
-    double* ball;         // mu, xi per centre
-    Ctrl* C;
-};
-
-struct BTable {
-    BJob* jobs;
-    Ctrl* out;            // gathered per-job control blocks (n_jobs)
-    int64_t* asm_start;   // prefix of nip
-    int64_t* col_start;   // prefix of nit
-    int64_t* both_start;  // prefix of 2*nit
-    int64_t* ball_start;  // prefix of nc
-    int* active;          // jobs not finished
-    int* pass;            // refinement pass counter (device, for graph replay)
-    int* n_act;           // length of the compacted list of unfinished jobs
-    int* act_jobs;        // unfinished jobs, in job order
-    int64_t* act_col;     // prefix of nit over act_jobs
-    int64_t* act_both;    // prefix of 2*nit over act_jobs
-    int n_jobs;
-    int max_outer;
-    float omega;
-    int pad;
-};
-
 namespace {
-
-constexpr int kItem = 256;
-constexpr int64_t kBatchMaxPadded = (int64_t)1 << 25;   // padded cells of one batched job
-constexpr int kWaves = kItem / 64;      // per-wave partial sums per work item
-
-#define SS4_GLOBAL __attribute__((address_space(1)))
-
-// Global-memory view of a pointer: with a wave-uniform base the loads and
-// stores take a 32-bit per-lane offset (every per-job array of the batched
-// layout stays below 4 GiB).
-template <typename T>
-__device__ __forceinline__ SS4_GLOBAL T* gbl(T* p) { return (SS4_GLOBAL T*)p; }
-
-// 16-byte record of the BF16 coefficients as a plain vector (HIP's uint4 is
-// a class that does not bind to global-address-space references)
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// floor(n / d) for n < 2^31 with M = ceil(2^63 / d): n*M/2^63 exceeds n/d by
-// less than 2^-32, and the fractional part of n/d is at most 1 - 1/d, so the
-// floor is exact for every d < 2^32.
-__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint64_t M)
-{
-    const uint64_t lo = (uint64_t)n * (uint32_t)M;
-    const uint64_t mid = (uint64_t)n * (uint32_t)(M >> 32) + (lo >> 32);
-    return (uint32_t)(mid >> 31);
-}
-
-__device__ __forceinline__ int find_job(const int64_t* start, int n, int64_t w)
-{
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (start[mid] <= w) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-// Work items of a global list (prefix `st` over `n` entries; entry a is job
-// map[a], or a without a map) dealt to the blocks per XCD: the list is cut
-// into one contiguous chunk per XCD (blocks are placed on the XCDs round
-// robin), and in each round the blocks of one XCD take consecutive items of
-// its chunk.  Rows that an item reads as neighbours (the rows beside it and
-// the planes and frames before and after it) belong to items that the same
-// XCD processes in the same or an adjacent round, so they are still in that
-// XCD's L2.  Calls body(job, first, last, step) for each job's run of this
-// block's items first, first+step, ... < last.
-template <typename Body>
-__device__ __forceinline__ void for_runs(const int64_t* st, const int* map, int n, Body&& body)
-{
-    const int64_t total = st[n];
-    const int nx = (int)gridDim.x < kXcd ? (int)gridDim.x : kXcd;
-    const int slots = (int)gridDim.x / nx;
-    if ((int)blockIdx.x >= nx * slots) return;
-    const int64_t chunk = (total + nx - 1) / nx;
-    const int64_t beg = (int64_t)(blockIdx.x % nx) * chunk;
-    const int64_t end = beg + chunk < total ? beg + chunk : total;
-    int64_t w = beg + blockIdx.x / nx;
-    if (w >= end) return;
-    int a = find_job(st, n, w);
-    while (w < end) {
-        while (st[a + 1] <= w) ++a;
-        const int64_t base = st[a];
-        const int64_t stop = st[a + 1] < end ? st[a + 1] : end;
-        body(map ? map[a] : a, (uint32_t)(w - base), (uint32_t)(stop - base), (uint32_t)slots);
-        w += (stop - w + slots - 1) / slots * slots;      // first item of this block at or after stop
-    }
-}
-
-__device__ __forceinline__ uint32_t bctile(const BJob& J, int colour, uint32_t q)
-{
-    return (((uint32_t)colour * (uint32_t)J.ntq + (q >> kTileShift)) * kTileFields) * kTileSlots +
-           (q & (kTileSlots - 1));
-}
-
-// One cell of colour `colour` in the flat numbering: q = r*half + m with r the
-// interior row (j,k,l) and m the slot; prow is the padded row index.
-struct Cell {
-    uint32_t prow;
-    int m, j, k, l, par;
-};
-
-// decode flat q of colour `colour`: returns false for an inactive slot
-__device__ __forceinline__ bool bdecode(const BJob& J, int colour, uint32_t q, Cell& c)
-{
-    if (q >= (uint32_t)J.ncq) return false;
-    const uint32_t r = fdiv(q, J.mg_half);
-    c.m = (int)(q - r * (uint32_t)J.half);
-    const uint32_t r2 = fdiv(r, J.mg_n2);
-    c.j = (int)(r - r2 * (uint32_t)J.n2) + 1;
-    const uint32_t r3 = fdiv(r2, J.mg_n3);
-    c.k = (int)(r2 - r3 * (uint32_t)J.n3) + 1;
-    c.l = (int)r3 + 1;
-    c.par = (colour + c.j + c.k + c.l) & 1;
-    c.prow = ((uint32_t)c.l * (uint32_t)J.p3 + (uint32_t)c.k) * (uint32_t)J.p2 + (uint32_t)c.j;
-    const int cnt = c.par ? (J.n1 + 1) >> 1 : J.n1 >> 1;
-    return c.m < cnt;
-}
-
 __global__ void kb_init(BTable T, double tol, int max_outer)
 {
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < T.n_jobs; j += gridDim.x * blockDim.x) {
@@ -522,87 +378,9 @@ __global__ __launch_bounds__(kBlock) void kb_unsplit(BTable T)
     });
 }
 
-// local rescaling of every job: one block per ball (global ball list)
-__device__ __forceinline__ bool bball(const BJob& J, const subsurf4d_centre& c, double r, int& lo0, int& lo1, int& lo2,
-                                      int& w0, int& w1, int64_t& count)
-{
-    if (c.frame < 0 || c.frame >= J.n4) return false;
-    const double cc[3] = {(double)c.x, (double)c.y, (double)c.z};
-    const int n[3] = {J.n1, J.n2, J.n3};
-    int lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-        int v = (int)floor(cc[a] - r);
-        lo[a] = v < 1 ? 1 : (v > n[a] ? n[a] : v);
-        v = (int)ceil(cc[a] + r) + 2;
-        hi[a] = v < 1 ? 1 : (v > n[a] ? n[a] : v);
-    }
-    lo0 = lo[0]; lo1 = lo[1]; lo2 = lo[2];
-    w0 = hi[0] - lo[0] + 1;
-    w1 = hi[1] - lo[1] + 1;
-    count = (int64_t)w0 * w1 * (hi[2] - lo[2] + 1);
-    return true;
-}
-
-template <int PHASE>
-__global__ __launch_bounds__(kBlock) void kb_rescale(BTable T, double r)
-{
-    __shared__ double s_lo[4], s_hi[4];
-    const int64_t total = T.ball_start[T.n_jobs];
-    const double r2 = [&] {
-#pragma clang fp contract(off)
-        return r * r;
-    }();
-    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-        const int jb = find_job(T.ball_start, T.n_jobs, w);
-        const BJob& J = T.jobs[jb];
-        const int mball = (int)(w - T.ball_start[jb]);
-        const subsurf4d_centre c = J.centres[mball];
-        int lo0, lo1, lo2, w0, w1;
-        int64_t count;
-        const bool ok = bball(J, c, r, lo0, lo1, lo2, w0, w1, count);
-        double mn = INFINITY, mx = -INFINITY, span = 0.0, mu = 0.0;
-        if (PHASE == 1 && ok) {
-            mu = J.ball[2 * mball];
-            span = J.ball[2 * mball + 1] - mu;
-        }
-        if (ok && !(PHASE == 1 && !(span >= 1e-12))) {
-            for (int64_t qq = threadIdx.x; qq < count; qq += blockDim.x) {
-                const int i = lo0 + (int)(qq % w0);
-                const int64_t q2 = qq / w0;
-                const int j = lo1 + (int)(q2 % w1);
-                const int k = lo2 + (int)(q2 / w1);
-                const double d2 = dist2_exact((double)(i - 1) - (double)c.x, (double)(j - 1) - (double)c.y,
-                                              (double)(k - 1) - (double)c.z);
-                if (!(d2 <= r2)) continue;
-                const int l = c.frame + 1;
-                const int64_t p = (((int64_t)l * J.p3 + k) * J.p2 + j) * J.p1 + i;
-                if (PHASE == 0) {
-                    const double v = J.u[p];
-                    mn = fmin(mn, v);
-                    mx = fmax(mx, v);
-                } else {
-                    const int64_t ii = (((int64_t)(l - 1) * J.n3 + (k - 1)) * J.n2 + (j - 1)) * J.n1 + (i - 1);
-                    if (J.owner[ii] == mball) J.u[p] = (J.u[p] - mu) / span;
-                }
-            }
-        }
-        if (PHASE == 0) {
-            mn = wave_min(mn);
-            mx = wave_max(mx);
-            if ((threadIdx.x & 63) == 0) { s_lo[threadIdx.x >> 6] = mn; s_hi[threadIdx.x >> 6] = mx; }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                J.ball[2 * mball] = fmin(fmin(s_lo[0], s_lo[1]), fmin(s_lo[2], s_lo[3]));
-                J.ball[2 * mball + 1] = fmax(fmax(s_hi[0], s_hi[1]), fmax(s_hi[2], s_hi[3]));
-            }
-            __syncthreads();
-        }
-    }
-}
+}  // namespace
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-}  // namespace
 
 // Workspace carving of one job in the batched layout.
 bool plan_batch_job(const int32_t n[4], int32_t nc, BJob* J, size_t* bytes)
@@ -626,6 +404,7 @@ bool plan_batch_job(const int32_t n[4], int32_t nc, BJob* J, size_t* bytes)
     b.nip = (b.npad + kItem - 1) / kItem;
     auto magic = [](uint32_t d) { return (((uint64_t)1 << 63) + d - 1) / d; };
     b.mg_half = magic((uint32_t)b.half);
+    b.mg_n1 = magic((uint32_t)n[0]);
     b.mg_n2 = magic((uint32_t)n[1]);
     b.mg_n3 = magic((uint32_t)n[2]);
     b.mg_p1 = magic((uint32_t)b.p1);
@@ -636,6 +415,7 @@ bool plan_batch_job(const int32_t n[4], int32_t nc, BJob* J, size_t* bytes)
     size_t off = 0;
     auto take = [&](size_t nbytes) { const size_t o = off; off += al256(nbytes); return o; };
     const size_t o_ctrl = take(sizeof(Ctrl));
+    const size_t o_ctrl2 = take(sizeof(Ctrl));
     const size_t o_pa = take(sizeof(double) * parts);
     const size_t o_pb = take(sizeof(double) * parts);
     const size_t o_ball = take(sizeof(double) * 2 * (size_t)(nc > 0 ? nc : 1));
@@ -648,6 +428,7 @@ bool plan_batch_job(const int32_t n[4], int32_t nc, BJob* J, size_t* bytes)
     const size_t o_db = take(sizeof(float) * b.nrow_pad * b.rsu);
     // offsets are stored as pointers relative to a null base until bound
     b.C = reinterpret_cast<Ctrl*>(o_ctrl);
+    b.C2 = reinterpret_cast<Ctrl*>(o_ctrl2);
     b.part_a = reinterpret_cast<double*>(o_pa);
     b.part_b = reinterpret_cast<double*>(o_pb);
     b.ball = reinterpret_cast<double*>(o_ball);
@@ -682,13 +463,35 @@ namespace {
 template <typename T>
 T* rebase(void* ws, T* off) { return reinterpret_cast<T*>(static_cast<char*>(ws) + reinterpret_cast<size_t>(off)); }
 
-struct GraphCache {
-    hipGraphExec_t exec = nullptr;
-};
-
 }  // namespace
 
-namespace {
+int bind_batch_job(const int32_t n[4], int32_t nc, void* ws, size_t ws_bytes, BJob* out)
+{
+    BJob J;
+    size_t need = 0;
+    if (!plan_batch_job(n, nc, &J, &need)) {
+        set_error("batched job: unsupported grid (at most 2^25 padded cells)");
+        return SUBSURF4D_ESHAPE;
+    }
+    if (ws_bytes < need) {
+        set_error("batched job: workspace too small (see subsurf4d_batch_workspace_bytes)");
+        return SUBSURF4D_EWORKSPACE;
+    }
+    J.C = rebase(ws, J.C);
+    J.C2 = rebase(ws, J.C2);
+    J.part_a = rebase(ws, J.part_a);
+    J.part_b = rebase(ws, J.part_b);
+    J.ball = rebase(ws, J.ball);
+    J.xr = rebase(ws, J.xr);
+    J.xb = rebase(ws, J.xb);
+    J.coef = rebase(ws, J.coef);
+    J.c16 = rebase(ws, J.c16);
+    J.rf = rebase(ws, J.rf);
+    J.dr = rebase(ws, J.dr);
+    J.db = rebase(ws, J.db);
+    *out = J;
+    return 0;
+}
 
 // Graph capture is not allowed on the legacy default stream: a batched step
 // called on it runs on a library-owned non-blocking stream (default priority,
@@ -708,8 +511,6 @@ hipStream_t side_stream()
     streams[dev] = st;
     return st;
 }
-
-}  // namespace
 
 int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf4d_step_params& sp,
                       subsurf4d_result* results, void* table, size_t table_bytes, hipStream_t s);
@@ -742,28 +543,8 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
     for (int q = 0; q < n_jobs; ++q) {
         const subsurf4d_batch_job& bj = jobs[q];
         BJob J;
-        size_t need = 0;
         const int nc = sp.rescale ? bj.n_centres : 0;
-        if (!plan_batch_job(bj.grid.n, nc, &J, &need)) {
-            set_error("batched step: unsupported grid");
-            return SUBSURF4D_ESHAPE;
-        }
-        if (bj.workspace_bytes < need) {
-            set_error("batched step: job workspace too small (see subsurf4d_batch_workspace_bytes)");
-            return SUBSURF4D_EWORKSPACE;
-        }
-        void* ws = bj.workspace;
-        J.C = rebase(ws, J.C);
-        J.part_a = rebase(ws, J.part_a);
-        J.part_b = rebase(ws, J.part_b);
-        J.ball = rebase(ws, J.ball);
-        J.xr = rebase(ws, J.xr);
-        J.xb = rebase(ws, J.xb);
-        J.coef = rebase(ws, J.coef);
-        J.c16 = rebase(ws, J.c16);
-        J.rf = rebase(ws, J.rf);
-        J.dr = rebase(ws, J.dr);
-        J.db = rebase(ws, J.db);
+        if (int rc = bind_batch_job(bj.grid.n, nc, bj.workspace, bj.workspace_bytes, &J)) return rc;
         J.th2 = sp.tau / (bj.grid.h * bj.grid.h);
         J.eps2 = sp.eps * sp.eps;
         J.inv_h = 1.0 / bj.grid.h;

@@ -81,6 +81,9 @@ int run_copy_probe(const void* src, void* dst, size_t bytes, int reps, double* m
 // batched windows (batch.hip)
 size_t batch_job_bytes(const int32_t n[4], int32_t nc);
 size_t batch_table_bytes(int32_t n_jobs);
+int run_batch_prepare(const subsurf4d_batch_prepare_job* jobs, int n_jobs, const subsurf4d_prepare_params& pp,
+                      double v, double R, double ball_r, int32_t* statuses, void* table, size_t table_bytes,
+                      hipStream_t s);
 int run_batch_step(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf4d_step_params& sp,
                    subsurf4d_result* results, void* table, size_t table_bytes, hipStream_t s);
 

@@ -7,11 +7,12 @@ the result is the final u, copied to the host.
 
 BatchServer: continuous batching.  Jobs that arrive while others run are
 admitted, first come first served, as soon as their device memory fits the
-HBM budget; an admitted job keeps G, u and its workspace resident until it
-finishes.  Every loop iteration advances all admitted jobs by one time step
-with one batched call (mixed precision, graph-replayed refinement passes), so
-the work of all resident jobs overlaps on the device; finished jobs hand
-their result to the host and free their memory at the step boundary.
+HBM budget; the jobs admitted together are prepared with one batched call,
+and an admitted job keeps G, u and its workspace resident until it finishes.
+Every loop iteration advances all admitted jobs by one time step with one
+batched call (mixed precision, graph-replayed refinement passes), so the work
+of all resident jobs overlaps on the device; finished jobs hand their result
+to the host and free their memory at the step boundary.
 
 PlainServer: the same jobs, first come first served, one at a time, each step
 an FP64 subsurf4d_step on its own (the plain per-job GPU path).
@@ -54,27 +55,31 @@ def window_bytes(n, nc):
 
 
 class _Shared:
-    """Preparation workspace and batch table shared by all jobs of a server."""
+    """Batch table shared by all calls of a server."""
 
     def __init__(self, max_jobs, device="cuda"):
         import torch
 
-        self.prep_ws = torch.empty(B.prepare_workspace_bytes(MAX_WINDOW, 2 * MAX_WINDOW[3]),
-                                   dtype=torch.uint8, device=device)
         self.table = torch.empty(B.batch_table_bytes(max_jobs), dtype=torch.uint8, device=device)
         self.max_jobs = max_jobs
 
 
-def admit_window(w: Window, pp, v, R, ball_r, shared: _Shared, batch=True, precision=B.MIXED):
-    img = w.img
-    if any(a > b for a, b in zip(img.n, MAX_WINDOW)):
-        raise ValueError(f"window {img.n} exceeds {MAX_WINDOW}")
-    job = B.Job(img.n, img.image, img.centres, img.seeds, batch=batch, shared_ws=shared.prep_ws,
-                precision=precision)
-    job.prepare(pp)
-    job.init(v=v, R=R, ball_r=ball_r)
-    w.state = job
-    return job
+def admit_windows(ws, pp, v, R, ball_r, shared: _Shared):
+    """Device state of the windows `ws` (one batched preparation call: owner
+    map, G, u0 rescaled)."""
+    jobs = []
+    for w in ws:
+        img = w.img
+        if any(a > b for a, b in zip(img.n, MAX_WINDOW)):
+            raise ValueError(f"window {img.n} exceeds {MAX_WINDOW}")
+        w.state = B.Job(img.n, img.image, img.centres, img.seeds, batch=True, shared_ws=False,
+                        precision=B.MIXED)
+        jobs.append(w.state)
+    for q in range(0, len(jobs), shared.max_jobs):
+        rc, st = B.prepare_batched(jobs[q:q + shared.max_jobs], pp, v, R, ball_r, shared.table)
+        if rc < 0 or any(x < 0 for x in st):
+            raise RuntimeError(f"batched preparation failed: {rc} {st}")
+    return jobs
 
 
 class BatchServer:
@@ -100,17 +105,22 @@ class BatchServer:
             if not realtime:
                 now = max(now, pending[0].arrival if pending and not running else now)
             # admit arrived jobs in order while they fit the budget and the table
-            while pending and pending[0].arrival <= now and len(running) < self.shared.max_jobs:
+            new = []
+            while pending and pending[0].arrival <= now and len(running) + len(new) < self.shared.max_jobs:
                 w = pending[0]
                 need = window_bytes(w.img.n, len(w.img.centres))
-                if used + need > self.budget and running:
+                if used + need > self.budget and (running or new):
                     break
                 pending.popleft()
                 w.nbytes = need
                 used += need
-                admit_window(w, self.pp, self.v, self.R, self.sp.ball_r, self.shared)
-                w.admitted = time.perf_counter() - t0
-                running.append(w)
+                new.append(w)
+            if new:
+                admit_windows(new, self.pp, self.v, self.R, self.sp.ball_r, self.shared)
+                ta = time.perf_counter() - t0
+                for w in new:
+                    w.admitted = ta
+                running.extend(new)
             if not running:
                 if pending:
                     wait = pending[0].arrival - (time.perf_counter() - t0)

@@ -1,0 +1,141 @@
+"""Batched preparation of many windows (owner map, G, u0 and its rescale in one
+sequence of launches) against the FP64 oracle, the single-job path, and
+itself (alone vs in a mix)."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import oracle as orc  # noqa: E402
+import synth  # noqa: E402
+from paper_2111_11866_amd import binding as B  # noqa: E402
+
+PP = B.PrepareParams(image_scale=1.0 / 255.0)
+SIZES = [(24, 30, 26, 3), (33, 25, 28, 5), (40, 40, 40, 5), (27, 35, 24, 9), (64, 24, 30, 4), (25, 25, 25, 3)]
+BALL_R = 8.0
+
+
+def H(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def orc_pp(p: B.PrepareParams):
+    return orc.PrepareParams(K=p.K, delta=p.delta, vartheta=p.vartheta, lam=p.lam, ball_r=p.ball_r,
+                             smooth_tau=p.smooth_tau, smooth_steps=p.smooth_steps,
+                             smooth_omega=p.smooth_omega, smooth_tol=p.smooth_tol)
+
+
+def windows(sizes, seed0=1000):
+    return [synth.window_job(n, seed0 + q, seed0 + 100000 + q) for q, n in enumerate(sizes)]
+
+
+def batched(imgs, pp=PP, v=1.0, R=0.0):
+    jobs = [B.Job(im.n, im.image, im.centres, im.seeds, precision=B.MIXED, batch=True, shared_ws=False)
+            for im in imgs]
+    table = torch.empty(B.batch_table_bytes(len(jobs)), dtype=torch.uint8, device="cuda")
+    rc, st = B.prepare_batched(jobs, pp, v, R, BALL_R, table)
+    return rc, st, jobs
+
+
+def oracle_prep(im, pp=PP, v=1.0, R=0.0):
+    I0 = im.image.astype(np.float64) * pp.image_scale
+    prep = orc.prepare(im.n, I0, im.centres, orc_pp(pp))
+    u0 = orc.init_u(im.n, im.seeds, v, R)
+    w = orc.rescale(im.n, u0, im.centres, BALL_R, prep["owner"])
+    return prep, w
+
+
+@pytest.fixture(scope="module")
+def imgs():
+    return windows(SIZES)
+
+
+def test_batched_prepare_matches_oracle(imgs):
+    rc, st, jobs = batched(imgs)
+    assert rc == 0 and st == [0] * len(imgs)
+    for im, j in zip(imgs, jobs):
+        prep, w = oracle_prep(im)
+        np.testing.assert_array_equal(H(j.owner), prep["owner"])
+        assert np.abs(H(j.G) - prep["G"]).max() <= 1e-12
+        # u0 and its rescale are exact decisions on exactly rounded values
+        np.testing.assert_array_equal(H(j.u), w)
+
+
+def test_batched_prepare_matches_single_job(imgs):
+    rc, st, jobs = batched(imgs)
+    assert rc == 0
+    for im, j in zip(imgs, jobs):
+        s = B.Job(im.n, im.image, im.centres, im.seeds, precision=B.MIXED)
+        assert s.prepare(PP) == 0
+        s.init(v=1.0, R=0.0, ball_r=BALL_R)
+        np.testing.assert_array_equal(H(j.owner), H(s.owner))
+        assert np.abs(H(j.G) - H(s.G)).max() <= 1e-13
+        np.testing.assert_array_equal(H(j.u), H(s.u))
+
+
+def test_batched_prepare_alone_equals_in_mix(imgs):
+    _, _, mix = batched(imgs)
+    for q in (0, 2, 5):
+        _, _, alone = batched([imgs[q]])
+        np.testing.assert_array_equal(H(alone[0].G), H(mix[q].G))
+        np.testing.assert_array_equal(H(alone[0].u), H(mix[q].u))
+        np.testing.assert_array_equal(H(alone[0].owner), H(mix[q].owner))
+
+
+def test_batched_prepare_two_smoothing_steps_and_cutoff():
+    """two heat steps per image and the R > 0 (scattered) initial function"""
+    pp = replace(PP, smooth_steps=2)
+    ims = windows([(26, 24, 25, 4), (30, 27, 24, 3)], seed0=2000)
+    rc, st, jobs = batched(ims, pp=pp, v=1.0, R=6.0)
+    assert rc == 0
+    for im, j in zip(ims, jobs):
+        prep, w = oracle_prep(im, pp=pp, v=1.0, R=6.0)
+        np.testing.assert_array_equal(H(j.owner), prep["owner"])
+        assert np.abs(H(j.G) - prep["G"]).max() <= 1e-12
+        np.testing.assert_array_equal(H(j.u), w)
+
+
+def test_batched_prepare_no_centres_and_f32_image():
+    im = synth.window_job((28, 26, 24, 3), 3000, 103000)
+    im32 = synth.Image4D(n=im.n, image=im.image.astype(np.float32), centres=im.centres[:0], seeds=im.seeds)
+    rc, st, jobs = batched([im32])
+    assert rc == 0
+    prep, w = oracle_prep(synth.Image4D(n=im.n, image=im.image.astype(np.float64), centres=im.centres[:0],
+                                        seeds=im.seeds))
+    assert (H(jobs[0].owner) == -1).all()
+    assert np.abs(H(jobs[0].G) - prep["G"]).max() <= 1e-12
+    np.testing.assert_array_equal(H(jobs[0].u), w)
+
+
+def test_batched_prepare_then_step(imgs):
+    """the prepared jobs step like jobs prepared one by one"""
+    sp = B.StepParams(precision=B.MIXED, refine_tol=1e-10, inner_sweeps=8)
+    rc, st, jobs = batched(imgs)
+    table = torch.empty(B.batch_table_bytes(len(jobs)), dtype=torch.uint8, device="cuda")
+    rc, res = B.step_batched(jobs, sp, table)
+    assert rc == 0 and all(r["status"] == 0 for r in res)
+    for im, j in zip(imgs, jobs):
+        s = B.Job(im.n, im.image, im.centres, im.seeds, precision=B.MIXED, batch=True)
+        s.prepare(PP)
+        s.init(v=1.0, R=0.0, ball_r=BALL_R)
+        B.step_batched([s], sp, table)
+        assert np.abs(H(j.u) - H(s.u)).max() <= 1e-10
+
+
+def test_batched_prepare_bad_arguments(imgs):
+    jobs = [B.Job(imgs[0].n, imgs[0].image, imgs[0].centres, imgs[0].seeds, precision=B.MIXED, batch=True,
+                  shared_ws=False)]
+    small = torch.empty(256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.Subsurf4dError):
+        B.prepare_batched(jobs, PP, 1.0, 0.0, BALL_R, small)
+    table = torch.empty(B.batch_table_bytes(1), dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.Subsurf4dError):
+        B.prepare_batched(jobs, replace(PP, lam=2.0), 1.0, 0.0, BALL_R, table)
+    with pytest.raises(B.Subsurf4dError):
+        B.prepare_batched(jobs, PP, 0.0, 0.0, BALL_R, table)
