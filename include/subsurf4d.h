@@ -110,6 +110,11 @@ typedef struct {
 /* subsurf4d_step_params.flags: launch the refinement passes of a batched step
  * one by one instead of replaying a captured HIP graph (same results). */
 #define SUBSURF4D_FLAG_NO_GRAPH 1
+/* subsurf4d_step_params.flags: use this work shape for the inner sweeps of a
+ * batched step instead of the autotuner's choice (same results): flat
+ * 256-cell items, or 256-slot columns marching through the frames. */
+#define SUBSURF4D_FLAG_SWEEP_FLAT 2
+#define SUBSURF4D_FLAG_SWEEP_MARCH 4
 
 /* Outcome of a solve.  Iterations are full red-black iterations. */
 typedef struct {

@@ -53,6 +53,8 @@ class StepParamsC(ctypes.Structure):
 
 
 FLAG_NO_GRAPH = 1
+FLAG_SWEEP_FLAT = 2
+FLAG_SWEEP_MARCH = 4
 
 
 class BatchJobC(ctypes.Structure):

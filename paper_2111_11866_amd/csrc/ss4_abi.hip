@@ -161,6 +161,10 @@ int check_step_params(const subsurf4d_step_params* p)
         if (!(p->refine_tol > 0.0)) return fail(SUBSURF4D_EINVAL, "refine_tol must be > 0");
         if (p->inner_sweeps < 1) return fail(SUBSURF4D_EINVAL, "inner_sweeps must be >= 1");
     }
+    const int known = SUBSURF4D_FLAG_NO_GRAPH | SUBSURF4D_FLAG_SWEEP_FLAT | SUBSURF4D_FLAG_SWEEP_MARCH;
+    if (p->flags & ~known) return fail(SUBSURF4D_EINVAL, "unknown flags");
+    if ((p->flags & SUBSURF4D_FLAG_SWEEP_FLAT) && (p->flags & SUBSURF4D_FLAG_SWEEP_MARCH))
+        return fail(SUBSURF4D_EINVAL, "at most one sweep shape flag");
     return 0;
 }
 

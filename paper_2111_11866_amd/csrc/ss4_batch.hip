@@ -244,6 +244,20 @@ __global__ __launch_bounds__(kBlock) void kb_residual_decide(BTable T)
 }
 
 // FP32 half-sweep of colour COLOR on the scaled correction system.
+// The relaxed update of one cell of the scaled correction system, shared by
+// both work shapes so that they give the same bits.
+__device__ __forceinline__ float sweep_cell(u32x4 cw, float s, float xl, float xr, float ym, float yp, float zm,
+                                            float zp, float tm, float tp, float om, float om1, float old)
+{
+    s += bf16_lo(cw.x) * xl + bf16_hi(cw.x) * xr;
+    s += bf16_lo(cw.y) * ym + bf16_hi(cw.y) * yp;
+    s += bf16_lo(cw.z) * zm + bf16_hi(cw.z) * zp;
+    s += bf16_lo(cw.w) * tm + bf16_hi(cw.w) * tp;
+    return om * s + om1 * old;
+}
+
+// FP32 half-sweep of colour COLOR, flat shape: a work item is 256
+// consecutive q of one colour.
 template <int COLOR>
 __global__ __launch_bounds__(kBlock) void kb_sweep(BTable T)
 {
@@ -261,13 +275,57 @@ __global__ __launch_bounds__(kBlock) void kb_sweep(BTable T)
             Cell c;
             if (!bdecode(J, COLOR, q, c)) continue;
             const uint32_t ui = c.prow * J.rsu + 1 + c.m;
-            const u32x4 cw = c16[cb + q];
-            float s = rf[cb + q];
-            s += bf16_lo(cw.x) * oth[ui - c.par] + bf16_hi(cw.x) * oth[ui + 1 - c.par];
-            s += bf16_lo(cw.y) * oth[ui - sy] + bf16_hi(cw.y) * oth[ui + sy];
-            s += bf16_lo(cw.z) * oth[ui - sz] + bf16_hi(cw.z) * oth[ui + sz];
-            s += bf16_lo(cw.w) * oth[ui - st] + bf16_hi(cw.w) * oth[ui + st];
-            own[ui] = om * s + om1 * own[ui];
+            own[ui] = sweep_cell(c16[cb + q], rf[cb + q], oth[ui - c.par], oth[ui + 1 - c.par], oth[ui - sy],
+                                 oth[ui + sy], oth[ui - sz], oth[ui + sz], oth[ui - st], oth[ui + st], om, om1,
+                                 own[ui]);
+        }
+    });
+}
+
+// FP32 half-sweep of colour COLOR, frame-marching shape: a work item is 256
+// consecutive slots qf = ((k-1)*N2 + (j-1))*half + m of one frame's flat
+// numbering, and each thread walks the frames l = 1..N4 of its slot (a 4D
+// tile of 256 slots x N4 frames).  The other colour's values of the slot at
+// l-1, l, l+1 stay in registers: they are the cell's t-neighbours and one of
+// its x-neighbours.  Cell (j,k,l) of slot m has q = (l-1)*nqf + qf.
+template <int COLOR>
+__global__ __launch_bounds__(kBlock) void kb_sweep_tm(BTable T)
+{
+    const float om = T.omega, om1 = 1.0f - T.omega;
+    for_runs(T.act_colf, T.act_jobs, *T.n_act, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
+        const BJob J = T.jobs[jb];
+        const uint32_t sy = J.rsu, sz = (uint32_t)J.p2 * J.rsu, st = sz * (uint32_t)J.p3;
+        SS4_GLOBAL float* own = gbl(COLOR ? J.db : J.dr);
+        SS4_GLOBAL const float* oth = gbl(static_cast<const float*>(COLOR ? J.dr : J.db));
+        const uint32_t cb = (uint32_t)COLOR * (uint32_t)J.ntq * kTileSlots;
+        SS4_GLOBAL const u32x4* c16 = gbl(reinterpret_cast<const u32x4*>(J.c16));
+        SS4_GLOBAL const float* rf = gbl(static_cast<const float*>(J.rf));
+        const uint32_t nqf = (uint32_t)J.nqf;
+        for (uint32_t item = i0; item < i1; item += step) {
+            const uint32_t qf = item * kItem + threadIdx.x;
+            if (qf >= nqf) continue;
+            const uint32_t r = fdiv(qf, J.mg_half);
+            const int m = (int)(qf - r * (uint32_t)J.half);
+            const uint32_t r2 = fdiv(r, J.mg_n2);
+            const int j = (int)(r - r2 * (uint32_t)J.n2) + 1;
+            const int k = (int)r2 + 1;
+            const uint32_t u0 = ((uint32_t)k * J.p2 + (uint32_t)j) * J.rsu + 1 + m;   // row (j,k,l=0)
+            float Bm = oth[u0];
+            float Bc = oth[u0 + st];
+            for (int l = 1; l <= J.n4; ++l) {
+                const uint32_t ui = u0 + (uint32_t)l * st;
+                const float Bp = oth[ui + st];
+                const int par = (COLOR + j + k + l) & 1;
+                const int cnt = par ? (J.n1 + 1) >> 1 : J.n1 >> 1;
+                if (m < cnt) {
+                    const uint32_t q = (uint32_t)(l - 1) * nqf + qf;
+                    const float xo = oth[par ? ui - 1 : ui + 1];
+                    own[ui] = sweep_cell(c16[cb + q], rf[cb + q], par ? xo : Bc, par ? Bc : xo, oth[ui - sy],
+                                         oth[ui + sy], oth[ui - sz], oth[ui + sz], Bm, Bp, om, om1, own[ui]);
+                }
+                Bm = Bc;
+                Bc = Bp;
+            }
         }
     });
 }
@@ -299,38 +357,45 @@ __global__ __launch_bounds__(kScan) void kb_compact(BTable T)
 {
     __shared__ int s_cnt[kScan];
     __shared__ int64_t s_sum[kScan];
+    __shared__ int64_t s_sumf[kScan];
     const int per = (T.n_jobs + kScan - 1) / kScan;
     const int lo = threadIdx.x * per;
     const int hi = lo + per < T.n_jobs ? lo + per : T.n_jobs;
     int cnt = 0;
-    int64_t sum = 0;
+    int64_t sum = 0, sumf = 0;
     for (int jb = lo; jb < hi; ++jb)
-        if (!T.jobs[jb].C->done) { ++cnt; sum += T.jobs[jb].nit; }
+        if (!T.jobs[jb].C->done) { ++cnt; sum += T.jobs[jb].nit; sumf += T.jobs[jb].nitf; }
     s_cnt[threadIdx.x] = cnt;
     s_sum[threadIdx.x] = sum;
+    s_sumf[threadIdx.x] = sumf;
     __syncthreads();
     for (int d = 1; d < kScan; d <<= 1) {            // inclusive Hillis-Steele scan
         const int c = threadIdx.x >= d ? s_cnt[threadIdx.x - d] : 0;
         const int64_t v = threadIdx.x >= d ? s_sum[threadIdx.x - d] : 0;
+        const int64_t vf = threadIdx.x >= d ? s_sumf[threadIdx.x - d] : 0;
         __syncthreads();
         s_cnt[threadIdx.x] += c;
         s_sum[threadIdx.x] += v;
+        s_sumf[threadIdx.x] += vf;
         __syncthreads();
     }
     int pos = s_cnt[threadIdx.x] - cnt;
-    int64_t base = s_sum[threadIdx.x] - sum;
+    int64_t base = s_sum[threadIdx.x] - sum, basef = s_sumf[threadIdx.x] - sumf;
     for (int jb = lo; jb < hi; ++jb) {
         if (T.jobs[jb].C->done) continue;
         T.act_jobs[pos] = jb;
         T.act_col[pos] = base;
         T.act_both[pos] = 2 * base;
+        T.act_colf[pos] = basef;
         ++pos;
         base += T.jobs[jb].nit;
+        basef += T.jobs[jb].nitf;
     }
     if (threadIdx.x == kScan - 1) {
         const int na = s_cnt[kScan - 1];
         T.act_col[na] = s_sum[kScan - 1];
         T.act_both[na] = 2 * s_sum[kScan - 1];
+        T.act_colf[na] = s_sumf[kScan - 1];
         *T.n_act = na;
     }
 }
@@ -411,6 +476,8 @@ bool plan_batch_job(const int32_t n[4], int32_t nc, BJob* J, size_t* bytes)
     b.mg_p2 = magic((uint32_t)b.p2);
     b.mg_p3 = magic((uint32_t)b.p3);
     b.nit = (b.ncq + kItem - 1) / kItem;
+    b.nqf = (int64_t)n[1] * n[2] * b.half;
+    b.nitf = (b.nqf + kItem - 1) / kItem;
     const int64_t parts = kWaves * (b.nip > 2 * b.nit ? b.nip : 2 * b.nit);
     size_t off = 0;
     auto take = [&](size_t nbytes) { const size_t o = off; off += al256(nbytes); return o; };
@@ -454,7 +521,7 @@ size_t batch_job_bytes(const int32_t n[4], int32_t nc)
 size_t batch_table_bytes(int32_t n_jobs)
 {
     const size_t nj = (size_t)(n_jobs > 0 ? n_jobs : 1);
-    return al256(sizeof(BJob) * nj) + al256(sizeof(Ctrl) * nj) + 6 * al256(sizeof(int64_t) * (nj + 1)) +
+    return al256(sizeof(BJob) * nj) + al256(sizeof(Ctrl) * nj) + 7 * al256(sizeof(int64_t) * (nj + 1)) +
            al256(sizeof(int) * nj) + 256;
 }
 
@@ -573,6 +640,7 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
     T.ball_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
     T.act_col = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
     T.act_both = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
+    T.act_colf = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
     T.act_jobs = reinterpret_cast<int*>(tb + off); off += al256(sizeof(int) * n_jobs);
     T.active = reinterpret_cast<int*>(tb + off);
     T.pass = T.active + 1;
@@ -600,47 +668,63 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
     kb_zero_d<<<g_zero, 256, 0, s>>>(T);
     SS4_LAUNCHED("batched: assemble");
 
-    // Launch-shape autotuner for the inner sweep: the first batch with a given
-    // signature times grids of 1, 2 and 4 times the resident size on its own
-    // data and keeps the fastest.  The grid only changes which block visits
-    // which work item, never a job's arithmetic; the corrections are zeroed
-    // again afterwards.
-    int g_sw = 0;
-    {
+    // Autotuner of the inner sweep's 4D tile shape and launch shape: the first
+    // batch with a given signature times both work shapes (flat 256-cell items,
+    // or 256-slot x N4-frame marching columns) at grids of 1, 2 and 4 times
+    // the resident size on its own data and keeps the fastest.  Shape and grid
+    // change only which thread updates which cell, never a job's arithmetic
+    // (the red-black iterate does not depend on the order within a colour);
+    // the corrections are zeroed again afterwards.  Flags can force a shape.
+    int g_sw = 0, shape = 0;
+    const int forced = (sp.flags & SUBSURF4D_FLAG_SWEEP_FLAT) ? 1 : (sp.flags & SUBSURF4D_FLAG_SWEEP_MARCH) ? 2 : 0;
+    auto sweep_pair = [&](int shp, int g) {
+        if (shp == 0) {
+            kb_sweep<0><<<g, kBlock, 0, s>>>(T);
+            kb_sweep<1><<<g, kBlock, 0, s>>>(T);
+        } else {
+            kb_sweep_tm<0><<<g, kBlock, 0, s>>>(T);
+            kb_sweep_tm<1><<<g, kBlock, 0, s>>>(T);
+        }
+    };
+    if (forced) {
+        shape = forced - 1;
+        g_sw = shape == 0 ? resident_grid(reinterpret_cast<const void*>(&kb_sweep<0>))
+                          : resident_grid(reinterpret_cast<const void*>(&kb_sweep_tm<0>));
+    } else {
         static std::mutex mu;
-        static std::map<std::pair<int, int64_t>, int> tuned;
+        static std::map<std::pair<int, int64_t>, std::pair<int, int>> tuned;
         const auto key = std::make_pair(n_jobs, col_start[n_jobs]);
         {
             std::lock_guard<std::mutex> g(mu);
             auto it = tuned.find(key);
-            if (it != tuned.end()) g_sw = it->second;
+            if (it != tuned.end()) { shape = it->second.first; g_sw = it->second.second; }
         }
         if (!g_sw) {
-            const int res = resident_grid(reinterpret_cast<const void*>(&kb_sweep<0>));
             hipEvent_t e0, e1;
             SS4_HIP(hipEventCreate(&e0));
             SS4_HIP(hipEventCreate(&e1));
             float best = 1e30f;
-            for (int mult = 1; mult <= 4; mult *= 2) {
-                const int g = res * mult;
-                kb_sweep<0><<<g, kBlock, 0, s>>>(T);
-                SS4_HIP(hipEventRecord(e0, s));
-                for (int rep = 0; rep < 2; ++rep) {
-                    kb_sweep<0><<<g, kBlock, 0, s>>>(T);
-                    kb_sweep<1><<<g, kBlock, 0, s>>>(T);
+            for (int shp = 0; shp < 2; ++shp) {
+                const int res = shp == 0 ? resident_grid(reinterpret_cast<const void*>(&kb_sweep<0>))
+                                         : resident_grid(reinterpret_cast<const void*>(&kb_sweep_tm<0>));
+                for (int mult = 1; mult <= 4; mult *= 2) {
+                    const int g = res * mult;
+                    sweep_pair(shp, g);
+                    SS4_HIP(hipEventRecord(e0, s));
+                    for (int rep = 0; rep < 2; ++rep) sweep_pair(shp, g);
+                    SS4_HIP(hipEventRecord(e1, s));
+                    SS4_HIP(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    SS4_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best) { best = ms; g_sw = g; shape = shp; }
                 }
-                SS4_HIP(hipEventRecord(e1, s));
-                SS4_HIP(hipEventSynchronize(e1));
-                float ms = 0.f;
-                SS4_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best) { best = ms; g_sw = g; }
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             kb_zero_d<<<g_zero, 256, 0, s>>>(T);
             SS4_LAUNCHED("batched: tuning");
             std::lock_guard<std::mutex> g(mu);
-            tuned[key] = g_sw;
+            tuned[key] = std::make_pair(shape, g_sw);
         }
     }
 
@@ -651,10 +735,7 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
         kb_residual<<<g_res, kBlock, 0, s>>>(T);
         kb_residual_decide<<<g_dec, kBlock, 0, s>>>(T);
         kb_compact<<<1, kScan, 0, s>>>(T);
-        for (int it = 0; it < m; ++it) {
-            kb_sweep<0><<<g_sw, kBlock, 0, s>>>(T);
-            kb_sweep<1><<<g_sw, kBlock, 0, s>>>(T);
-        }
+        for (int it = 0; it < m; ++it) sweep_pair(shape, g_sw);
         kb_update<<<g_up, kBlock, 0, s>>>(T);
         kb_next_pass<<<1, 64, 0, s>>>(T);
     };

@@ -15,6 +15,7 @@ struct BJob {
     int64_t ncq;          // flat cells of one colour (incl. inactive slots)
     int64_t ntq;          // 128-tiles of one colour
     int64_t nip, nit;     // items over padded cells / over one colour
+    int64_t nqf, nitf;    // one frame's flat cells of one colour, and its items (marching shape)
     uint64_t mg_half, mg_n1, mg_n2, mg_n3, mg_p1, mg_p2, mg_p3;   // ceil(2^63 / d) for the index divisions
     double th2, eps2, inv_h;
     const double* G;
@@ -53,6 +54,7 @@ struct BTable {
     int* act_jobs;        // unfinished jobs, in job order
     int64_t* act_col;     // prefix of nit over act_jobs
     int64_t* act_both;    // prefix of 2*nit over act_jobs
+    int64_t* act_colf;    // prefix of nitf over act_jobs
     int n_jobs;
     int max_outer;
     float omega;

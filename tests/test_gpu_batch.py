@@ -99,6 +99,28 @@ def test_graph_replays_equal_eager(batch):
         assert np.array_equal(a, b) and np.array_equal(a, c)
 
 
+def test_sweep_shapes_give_the_same_bits(batch):
+    """Both work shapes of the inner sweep (flat items, frame-marching
+    columns) and the autotuner's choice give bitwise the same step."""
+    from dataclasses import replace
+
+    jobs, u0 = batch
+    out = []
+    for flags in (0, B.FLAG_SWEEP_FLAT, B.FLAG_SWEEP_MARCH, B.FLAG_SWEEP_MARCH | B.FLAG_NO_GRAPH):
+        for j, u in zip(jobs, u0):
+            j.u.copy_(u)
+        rc, res = run(jobs, replace(SP, flags=flags))
+        assert rc == 0
+        out.append([H(j.u) for j in jobs])
+    for per_job in zip(*out):
+        for other in per_job[1:]:
+            assert np.array_equal(per_job[0], other)
+    with pytest.raises(B.Subsurf4dError):
+        run(jobs, replace(SP, flags=B.FLAG_SWEEP_FLAT | B.FLAG_SWEEP_MARCH))
+    with pytest.raises(B.Subsurf4dError):
+        run(jobs, replace(SP, flags=64))
+
+
 def test_batched_several_steps_stay_bounded(batch):
     jobs, u0 = batch
     for j, u in zip(jobs, u0):
