@@ -215,6 +215,21 @@ int subsurf4d_step(const subsurf4d_grid* grid, const double* G, const subsurf4d_
                    void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * The same step with Dirichlet data that changes in time (the boundary
+ * condition of the problem statement, Sec. 3.1, with u^D a function of t; the
+ * convergence test of Sec. 3.4 uses the exact solution): u's ghost layer holds
+ * u^{n-1} on the boundary and feeds the boundary-face gradients, the ghost
+ * layer of u_dirichlet (device, padded; its interior is not read) holds u^D of
+ * the new level and enters the system.  On return u's ghost layer holds the
+ * new level's u^D, so consecutive steps chain.  u_dirichlet must not alias u.
+ * Everything else as subsurf4d_step.
+ */
+int subsurf4d_step_dirichlet(const subsurf4d_grid* grid, const double* G, const double* u_dirichlet,
+                             const subsurf4d_centre* centres, int32_t n_centres, const int32_t* owner, double* u,
+                             const subsurf4d_step_params* params, subsurf4d_result* result, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
+/*
  * The linear solve alone (Sec. 3.2.2 red-black SOR) for externally given
  * coefficients: coef (device, interior x 8, face order as above), b (device,
  * interior; Dirichlet terms already included), u (device, padded; interior =

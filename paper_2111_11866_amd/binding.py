@@ -28,7 +28,7 @@ EXPORTED = (
     "subsurf4d_assemble", "subsurf4d_step", "subsurf4d_solve", "subsurf4d_status_string",
     "subsurf4d_last_error", "subsurf4d_version", "subsurf4d_timing", "subsurf4d_copy_probe",
     "subsurf4d_batch_workspace_bytes", "subsurf4d_batch_table_bytes", "subsurf4d_step_batched",
-    "subsurf4d_prepare_workspace_bytes", "subsurf4d_prepare_batched",
+    "subsurf4d_prepare_workspace_bytes", "subsurf4d_prepare_batched", "subsurf4d_step_dirichlet",
 )
 
 
@@ -150,6 +150,8 @@ def lib():
         L.subsurf4d_assemble.argtypes = [ctypes.POINTER(Grid), P, P, ctypes.POINTER(StepParamsC), P, P, P]
         L.subsurf4d_step.argtypes = [ctypes.POINTER(Grid), P, P, I, P, P, ctypes.POINTER(StepParamsC),
                                      ctypes.POINTER(Result), P, SZ, P]
+        L.subsurf4d_step_dirichlet.argtypes = [ctypes.POINTER(Grid), P, P, P, I, P, P,
+                                               ctypes.POINTER(StepParamsC), ctypes.POINTER(Result), P, SZ, P]
         L.subsurf4d_solve.argtypes = [ctypes.POINTER(Grid), P, P, P, ctypes.POINTER(StepParamsC),
                                       ctypes.POINTER(Result), P, SZ, P]
         L.subsurf4d_status_string.argtypes = [ctypes.c_int]
@@ -262,6 +264,15 @@ def step(n, h, G, centres, n_centres, owner, u, params: StepParams, ws, stream=N
     _check(lib().subsurf4d_step(ctypes.byref(grid(n, h)), _p(G), _p(centres), int(n_centres), _p(owner),
                                 _p(u), ctypes.byref(params.c()), ctypes.byref(res), _p(ws), ws.numel(),
                                 _stream(stream)))
+    return res.as_dict()
+
+
+def step_dirichlet(n, h, G, ub, centres, n_centres, owner, u, params: StepParams, ws, stream=None) -> dict:
+    """One step whose new level takes its Dirichlet data from ub's ghost layer."""
+    res = Result()
+    _check(lib().subsurf4d_step_dirichlet(ctypes.byref(grid(n, h)), _p(G), _p(ub), _p(centres), int(n_centres),
+                                          _p(owner), _p(u), ctypes.byref(params.c()), ctypes.byref(res), _p(ws),
+                                          ws.numel(), _stream(stream)))
     return res.as_dict()
 
 

@@ -294,12 +294,12 @@ int subsurf4d_assemble(const subsurf4d_grid* grid, const double* G, const double
     SS4_GUARD_END
 }
 
-int subsurf4d_step(const subsurf4d_grid* grid, const double* G, const subsurf4d_centre* centres,
-                   int32_t n_centres, const int32_t* owner, double* u, const subsurf4d_step_params* params,
-                   subsurf4d_result* result, void* workspace, size_t workspace_bytes, void* stream)
+namespace {
+
+int step_common(const subsurf4d_grid* grid, const double* G, const double* ub, const subsurf4d_centre* centres,
+                int32_t n_centres, const int32_t* owner, double* u, const subsurf4d_step_params* params,
+                subsurf4d_result* result, void* workspace, size_t workspace_bytes, void* stream)
 {
-    SS4_GUARD_BEGIN
-    g_error.clear();
     if (int rc = check_grid(grid)) return rc;
     if (!G || !u) return fail(SUBSURF4D_EINVAL, "NULL argument");
     if (int rc = check_step_params(params)) return rc;
@@ -310,8 +310,34 @@ int subsurf4d_step(const subsurf4d_grid* grid, const double* G, const subsurf4d_
     if (!plan_workspace(grid->n, nc, params->precision, &P)) return fail(SUBSURF4D_ESHAPE, "grid too large");
     if (int rc = check_ws(P, workspace, workspace_bytes)) return rc;
     subsurf4d_result tmp;
-    return run_step(P, grid->h, G, centres, nc, owner, u, *params, result ? result : &tmp, workspace,
+    return run_step(P, grid->h, G, ub, centres, nc, owner, u, *params, result ? result : &tmp, workspace,
                     static_cast<hipStream_t>(stream));
+}
+
+}  // namespace
+
+int subsurf4d_step(const subsurf4d_grid* grid, const double* G, const subsurf4d_centre* centres,
+                   int32_t n_centres, const int32_t* owner, double* u, const subsurf4d_step_params* params,
+                   subsurf4d_result* result, void* workspace, size_t workspace_bytes, void* stream)
+{
+    SS4_GUARD_BEGIN
+    g_error.clear();
+    return step_common(grid, G, nullptr, centres, n_centres, owner, u, params, result, workspace, workspace_bytes,
+                       stream);
+    SS4_GUARD_END
+}
+
+int subsurf4d_step_dirichlet(const subsurf4d_grid* grid, const double* G, const double* u_dirichlet,
+                             const subsurf4d_centre* centres, int32_t n_centres, const int32_t* owner, double* u,
+                             const subsurf4d_step_params* params, subsurf4d_result* result, void* workspace,
+                             size_t workspace_bytes, void* stream)
+{
+    SS4_GUARD_BEGIN
+    g_error.clear();
+    if (!u_dirichlet) return fail(SUBSURF4D_EINVAL, "NULL Dirichlet data");
+    if (u_dirichlet == u) return fail(SUBSURF4D_EINVAL, "Dirichlet data must be a separate array (or use subsurf4d_step)");
+    return step_common(grid, G, u_dirichlet, centres, n_centres, owner, u, params, result, workspace,
+                       workspace_bytes, stream);
     SS4_GUARD_END
 }
 

@@ -64,8 +64,10 @@ int run_rescale(const WsPlan& P, const subsurf4d_centre* centres, int nc, double
 // time step and solve (solve.hip)
 int run_assemble_export(const Layout& L, double h, const double* G, const double* u,
                         const subsurf4d_step_params& sp, double* coef, double* b, hipStream_t s);
-int run_step(const WsPlan& P, double h, const double* G, const subsurf4d_centre* centres, int nc,
-             const int32_t* owner, double* u, const subsurf4d_step_params& sp,
+// ub: padded array whose ghost layer holds the new level's Dirichlet data
+// (NULL: u's own ghost layer serves both as gradient data and Dirichlet data)
+int run_step(const WsPlan& P, double h, const double* G, const double* ub, const subsurf4d_centre* centres,
+             int nc, const int32_t* owner, double* u, const subsurf4d_step_params& sp,
              subsurf4d_result* res, void* ws, hipStream_t s);
 int run_solve(const WsPlan& P, const double* coef, const double* b, double* u,
               const subsurf4d_step_params& sp, subsurf4d_result* res, void* ws, hipStream_t s);
@@ -74,8 +76,8 @@ int run_solve(const WsPlan& P, const double* coef, const double* b, double* u,
 int run_sor_loop(const WsPlan& P, const subsurf4d_step_params& sp, void* ws, hipStream_t s,
                  subsurf4d_result* res);
 int run_unsplit(const WsPlan& P, double* u, void* ws, hipStream_t s);
-int launch_assembly(const WsPlan& P, double h, const double* G, const double* w, const subsurf4d_step_params& sp,
-                    void* coef16, void* ws, hipStream_t s);
+int launch_assembly(const WsPlan& P, double h, const double* G, const double* w, const double* ub,
+                    const subsurf4d_step_params& sp, void* coef16, void* ws, hipStream_t s);
 int run_copy_probe(const void* src, void* dst, size_t bytes, int reps, double* ms, hipStream_t s);
 
 // batched windows (batch.hip)
@@ -88,7 +90,7 @@ int run_batch_step(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf4d_
                    subsurf4d_result* results, void* table, size_t table_bytes, hipStream_t s);
 
 // mixed precision (mixed.hip)
-int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
+int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w, const double* ub,
                     const subsurf4d_step_params& sp, subsurf4d_result* res, void* ws,
                     hipStream_t s);
 

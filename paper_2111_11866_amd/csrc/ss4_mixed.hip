@@ -199,8 +199,8 @@ __global__ void k_fill_f32(float* a, int64_t n)
 
 }  // namespace
 
-int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w, const subsurf4d_step_params& sp,
-                    subsurf4d_result* res, void* ws, hipStream_t s)
+int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w, const double* ub,
+                    const subsurf4d_step_params& sp, subsurf4d_result* res, void* ws, hipStream_t s)
 {
     const Layout& L = P.L;
     Ctrl* C = ws_ptr<Ctrl>(ws, P.ctrl);
@@ -221,7 +221,7 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
     a.max_outer = max_outer;
 
     k_ctrl_init<<<1, 64, 0, s>>>(C, sp.refine_tol, max_outer);
-    int rc = launch_assembly(P, h, G, w, sp, ws_ptr<void>(ws, P.coef16), ws, s);
+    int rc = launch_assembly(P, h, G, w, ub, sp, ws_ptr<void>(ws, P.coef16), ws, s);
     if (rc < 0) return rc;
     k_fill_f32<<<grid_for(L.usplit), kBlock, 0, s>>>(a.dr, L.usplit);
     k_fill_f32<<<grid_for(L.usplit), kBlock, 0, s>>>(a.db, L.usplit);

@@ -19,7 +19,8 @@ struct AsmArgs {
     double eps2;      // eps^2
     double inv_h;
     const double* G;  // 4 x padded
-    const double* w;  // padded u^{resc;n-1}
+    const double* w;  // padded u^{resc;n-1} (its ghosts feed the boundary-face gradients)
+    const double* ub; // padded; ghost layer = Dirichlet data of the new level (== w when not separate)
     double* ured0;
     double* ured1;
     double* ublack;
@@ -32,9 +33,9 @@ struct AsmArgs {
     Ctrl* C;
 };
 
-// One thread per padded cell.  Ghost cells only copy their Dirichlet value
-// into the colour-split u; interior cells compute the 8 coefficients from the
-// 33-point neighbourhood of w and G on the 8 faces.
+// One thread per padded cell.  Ghost cells only copy the new level's Dirichlet
+// value into the colour-split u; interior cells compute the 8 coefficients
+// from the 33-point neighbourhood of w and G on the 8 faces.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
 {
@@ -54,12 +55,13 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
         const int colour = (i + j + k + l) & 1;
         const int m = (i - 1) >> 1;
         const double w0 = a.w[p];
-        if (MODE == kSplit) {
-            const int64_t us = prow * L.rs + L.xoff + m;
-            if (colour == 0) { a.ured0[us] = w0; a.ured1[us] = w0; }
-            else a.ublack[us] = w0;
-        }
         const bool inside = i >= 1 && i <= L.n1 && j >= 1 && j <= L.n2 && k >= 1 && k <= L.n3 && l >= 1 && l <= L.n4;
+        if (MODE == kSplit) {
+            const double v0 = inside ? w0 : a.ub[p];
+            const int64_t us = prow * L.rs + L.xoff + m;
+            if (colour == 0) { a.ured0[us] = v0; a.ured1[us] = v0; }
+            else a.ublack[us] = v0;
+        }
         if (!inside) continue;
         const int idx[4] = {i, j, k, l};
         const int nn[4] = {L.n1, L.n2, L.n3, L.n4};
@@ -103,12 +105,16 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
         double D = 1.0;
 #pragma unroll
         for (int f = 0; f < 8; ++f) D += c[f];
+        // right-hand side and residual of the initial iterate: Dirichlet
+        // neighbours take the new level's data
         double bfull = w0, off = 0.0;
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
-            off += c[2 * d] * wm[d] + c[2 * d + 1] * wp[d];
-            if (idx[d] == 1) bfull += c[2 * d] * wm[d];
-            if (idx[d] == nn[d]) bfull += c[2 * d + 1] * wp[d];
+            const double vm = idx[d] == 1 ? a.ub[p - sd[d]] : wm[d];
+            const double vp = idx[d] == nn[d] ? a.ub[p + sd[d]] : wp[d];
+            off += c[2 * d] * vm + c[2 * d + 1] * vp;
+            if (idx[d] == 1) bfull += c[2 * d] * vm;
+            if (idx[d] == nn[d]) bfull += c[2 * d + 1] * vp;
         }
         const double r0 = (w0 + off) - D * w0;
         acc_b += bfull * bfull;
@@ -568,6 +574,21 @@ __global__ __launch_bounds__(kBlock) void k_unsplit(Layout L, const double* ured
     }
 }
 
+// ghost layer of ub -> ghost layer of u
+__global__ __launch_bounds__(kBlock) void k_copy_ghosts(Layout L, const double* __restrict__ ub, double* u)
+{
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < L.npad; p += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(p % L.p1);
+        const int64_t prow = p / L.p1;
+        const int j = (int)(prow % L.p2);
+        const int64_t t2 = prow / L.p2;
+        const int k = (int)(t2 % L.p3);
+        const int l = (int)(t2 / L.p3);
+        const bool inside = i >= 1 && i <= L.n1 && j >= 1 && j <= L.n2 && k >= 1 && k <= L.n3 && l >= 1 && l <= L.n4;
+        if (!inside) u[p] = ub[p];
+    }
+}
+
 int sweep_grid(const Layout& L, int variant)
 {
     int64_t work;
@@ -735,6 +756,7 @@ int run_assemble_export(const Layout& L, double h, const double* G, const double
     a.inv_h = 1.0 / h;
     a.G = G;
     a.w = u;
+    a.ub = u;
     a.coef_nat = coef;
     a.b_nat = b;
     k_assemble<kNatural><<<grid_for(L.npad), kBlock, 0, s>>>(a);
@@ -742,8 +764,8 @@ int run_assemble_export(const Layout& L, double h, const double* G, const double
     return 0;
 }
 
-int launch_assembly(const WsPlan& P, double h, const double* G, const double* w, const subsurf4d_step_params& sp,
-                    void* coef16, void* ws, hipStream_t s)
+int launch_assembly(const WsPlan& P, double h, const double* G, const double* w, const double* ub,
+                    const subsurf4d_step_params& sp, void* coef16, void* ws, hipStream_t s)
 {
     AsmArgs a{};
     a.L = P.L;
@@ -752,6 +774,7 @@ int launch_assembly(const WsPlan& P, double h, const double* G, const double* w,
     a.inv_h = 1.0 / h;
     a.G = G;
     a.w = w;
+    a.ub = ub ? ub : w;
     a.ured0 = ws_ptr<double>(ws, P.ured0);
     a.ured1 = ws_ptr<double>(ws, P.ured1);
     a.ublack = ws_ptr<double>(ws, P.ublack);
@@ -765,15 +788,15 @@ int launch_assembly(const WsPlan& P, double h, const double* G, const double* w,
     return 0;
 }
 
-int run_step(const WsPlan& P, double h, const double* G, const subsurf4d_centre* centres, int nc,
-             const int32_t* owner, double* u, const subsurf4d_step_params& sp, subsurf4d_result* res,
+int run_step(const WsPlan& P, double h, const double* G, const double* ub, const subsurf4d_centre* centres,
+             int nc, const int32_t* owner, double* u, const subsurf4d_step_params& sp, subsurf4d_result* res,
              void* ws, hipStream_t s)
 {
     const Layout& L = P.L;
     Ctrl* C = ws_ptr<Ctrl>(ws, P.ctrl);
     int rc;
     if (sp.precision == SUBSURF4D_MIXED) {
-        rc = run_mixed_solve(P, h, G, u, sp, res, ws, s);
+        rc = run_mixed_solve(P, h, G, u, ub, sp, res, ws, s);
         if (rc < 0) return rc;
         rc = run_unsplit(P, u, ws, s);
         if (rc < 0) return rc;
@@ -782,12 +805,17 @@ int run_step(const WsPlan& P, double h, const double* G, const subsurf4d_centre*
         int max_iter;
         effective_stop(sp, &tol, &max_iter);
         k_ctrl_init<<<1, 64, 0, s>>>(C, tol, max_iter);
-        rc = launch_assembly(P, h, G, u, sp, nullptr, ws, s);
+        rc = launch_assembly(P, h, G, u, ub, sp, nullptr, ws, s);
         if (rc < 0) return rc;
         rc = run_sor_loop(P, sp, ws, s, res);
         if (rc < 0) return rc;
         rc = run_unsplit(P, u, ws, s);
         if (rc < 0) return rc;
+    }
+    if (ub && ub != u) {
+        // the new level carries its Dirichlet data in its ghost layer
+        k_copy_ghosts<<<grid_for(L.npad), kBlock, 0, s>>>(L, ub, u);
+        SS4_LAUNCHED("ghost layer");
     }
     if (sp.rescale && nc > 0) {
         const int r2 = run_rescale(P, centres, nc, sp.ball_r, owner, u, ws, s);

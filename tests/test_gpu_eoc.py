@@ -1,0 +1,63 @@
+"""Convergence test of Sec. 3.4 on the GPU: the whole time step (assembly with
+eps = h^2, red-black SOR, time-dependent Dirichlet data) against the oracle's
+run of the same problem, and second-order convergence with errors below the
+paper's table (tests/golden/eoc_table.json) up to N = 80."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import oracle as orc  # noqa: E402
+from paper_2111_11866_amd import binding as B  # noqa: E402
+from paper_2111_11866_amd import eoc  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rows():
+    with open(os.path.join(HERE, "golden", "eoc_table.json")) as f:
+        return json.load(f)["rows"]
+
+
+@pytest.mark.parametrize("N,steps", [(10, 1), (20, 4)])
+def test_eoc_error_matches_oracle(N, steps):
+    e_gpu, its_gpu, _ = eoc.run(N, steps)
+    e_orc, its_orc = orc.eoc_run(N, steps)
+    assert its_gpu == its_orc
+    assert abs(e_gpu - e_orc) <= 1e-9 * e_orc, (e_gpu, e_orc)
+
+
+def test_eoc_second_order_to_n80():
+    tab = rows()
+    errs = [eoc.run(N, steps)[0] for N, steps in ((20, 4), (40, 16), (80, 64))]
+    assert errs[1] <= tab[2]["error"] and errs[2] <= tab[3]["error"]
+    assert np.log2(errs[0] / errs[1]) >= 1.8 and np.log2(errs[1] / errs[2]) >= 1.8
+
+
+def test_mixed_precision_eoc_matches_fp64():
+    """the mixed-precision step refined to 1e-11 gives the same error"""
+    e64 = eoc.run(20, 4)[0]
+    emx = eoc.run(20, 4, precision=B.MIXED)[0]
+    assert abs(emx - e64) <= 1e-6 * e64
+
+
+def test_step_dirichlet_checks():
+    n = (6, 5, 4, 3)
+    u = torch.zeros(B.padded_shape(n), dtype=torch.float64, device="cuda")
+    G = torch.ones((4,) + B.padded_shape(n), dtype=torch.float64, device="cuda")
+    ws = B.alloc_workspace(n)
+    with pytest.raises(B.Subsurf4dError):
+        B.step_dirichlet(n, 1.0, G, u, None, 0, None, u, B.StepParams(rescale=False), ws)
+    # with ub == u's own ghosts the step equals subsurf4d_step bitwise
+    rng = np.random.default_rng(5)
+    w = torch.from_numpy(rng.uniform(0, 1, B.padded_shape(n))).to("cuda")
+    a, b = w.clone(), w.clone()
+    B.step(n, 1.0, G, None, 0, None, a, B.StepParams(rescale=False), ws)
+    B.step_dirichlet(n, 1.0, G, w.clone(), None, 0, None, b, B.StepParams(rescale=False), ws)
+    assert torch.equal(a, b)
