@@ -208,12 +208,8 @@ def make_windows(rate, count, first_job=0, seed=7):
     import synth
 
     t, sizes = synth.serving_stream(rate, count, seed=seed, first_job=first_job)
-    wins = []
-    for q, (ta, n) in enumerate(zip(t, sizes)):
-        j = first_job + q
-        img = synth.window_job(n, 200000 + j, 300000 + j)
-        wins.append(Window(jid=j, arrival=float(ta), img=img))
-    return wins
+    imgs = synth.serving_windows(sizes, first_job)
+    return [Window(jid=first_job + q, arrival=float(ta), img=img) for q, (ta, img) in enumerate(zip(t, imgs))]
 
 
 def default_params():

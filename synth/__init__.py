@@ -13,4 +13,5 @@ from synth.gen import (  # noqa: F401
     window_job,
     windows_cfg4,
     serving_stream,
+    serving_windows,
 )

@@ -14,6 +14,8 @@ from __future__ import annotations
 
 from dataclasses import dataclass, field
 
+import os
+
 import numpy as np
 
 CENTRE_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("z", "<f4"), ("frame", "<i4")])
@@ -226,16 +228,33 @@ def window_job(n, geom_seed, noise_seed, sigma=1.5, background=20.0, extra_rate=
                    meta=dict(geom_seed=geom_seed, noise_seed=noise_seed))
 
 
+def _pool_map(fn, items):
+    """map over a thread pool: windows are independent and seeded per job, so
+    the output does not depend on the number of threads"""
+    from concurrent.futures import ThreadPoolExecutor
+
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(fn, items))
+
+
+def _cfg4_window(j):
+    r = np.random.default_rng(1000 + j)
+    n = (int(r.integers(24, 65)), int(r.integers(24, 65)), int(r.integers(24, 65)), int(r.integers(3, 10)))
+    return window_job(n, 1000 + j, 100000 + j)
+
+
 def windows_cfg4(count=2048, first=0):
     """Batched workload: window j has x,y,z ~ U{24..64}, t ~ U{3..9} (seed 1000+j),
     content seeds 1000+j (geometry) and 100000+j (noise)."""
-    out = []
-    for j in range(first, first + count):
-        r = np.random.default_rng(1000 + j)
-        n = (int(r.integers(24, 65)), int(r.integers(24, 65)), int(r.integers(24, 65)),
-             int(r.integers(3, 10)))
-        out.append(window_job(n, 1000 + j, 100000 + j))
-    return out
+    return _pool_map(_cfg4_window, range(first, first + count))
+
+
+def serving_windows(sizes, first_job=0):
+    """Images of serving jobs first_job, first_job+1, ... with the given sizes
+    (content seeds 200000+j and 300000+j)."""
+    return _pool_map(lambda q: window_job(sizes[q], 200000 + first_job + q, 300000 + first_job + q),
+                     range(len(sizes)))
 
 
 def serving_stream(rate, count, seed=7, median=(40, 40, 40, 5), log_sigma=0.4,
