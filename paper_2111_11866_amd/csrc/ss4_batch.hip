@@ -61,6 +61,7 @@ __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
         SS4_GLOBAL double* xb = gbl(J.xb);
         SS4_GLOBAL double* coef = gbl(J.coef);
         SS4_GLOBAL u32x4* c16 = gbl(reinterpret_cast<u32x4*>(J.c16));
+        SS4_GLOBAL float* rf = gbl(J.rf);
         SS4_GLOBAL double* pa = gbl(J.part_a);
         SS4_GLOBAL double* pb = gbl(J.part_b);
         const uint32_t npad = (uint32_t)J.npad;
@@ -138,6 +139,8 @@ __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
                     for (int f = 0; f < 8; ++f) coef[ci + f * kTileSlots] = c[f];
                     coef[ci + 8 * kTileSlots] = w0;
                     const double inv = 1.0 / D;
+                    // scaled residual of the initial iterate: the first refinement pass starts from it
+                    rf[(uint32_t)colour * (uint32_t)J.ntq * kTileSlots + qf] = (float)(r0 / D);
                     uint32_t hb[8];
 #pragma unroll
                     for (int f = 0; f < 8; ++f) hb[f] = bf16_bits((float)(c[f] * inv));
@@ -728,16 +731,18 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
         }
     }
 
-    // one refinement pass = residual (decides), m inner iterations, update;
-    // captured once as a graph and replayed until every job has finished
+    // one refinement pass = m inner iterations, update, FP64 residual of the
+    // new iterate, per-job decision, compaction (the assembly supplied the
+    // residual and the decision of the initial iterate); captured once as a
+    // graph and replayed until every job has finished
     const bool eager = (sp.flags & SUBSURF4D_FLAG_NO_GRAPH) != 0;
     auto enqueue_pass = [&]() {
-        kb_residual<<<g_res, kBlock, 0, s>>>(T);
-        kb_residual_decide<<<g_dec, kBlock, 0, s>>>(T);
-        kb_compact<<<1, kScan, 0, s>>>(T);
         for (int it = 0; it < m; ++it) sweep_pair(shape, g_sw);
         kb_update<<<g_up, kBlock, 0, s>>>(T);
         kb_next_pass<<<1, 64, 0, s>>>(T);
+        kb_residual<<<g_res, kBlock, 0, s>>>(T);
+        kb_residual_decide<<<g_dec, kBlock, 0, s>>>(T);
+        kb_compact<<<1, kScan, 0, s>>>(T);
     };
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
