@@ -37,3 +37,39 @@ def test_host_queries():
     assert B.workspace_bytes((0, 24, 24, 8)) == 0
     assert B.workspace_bytes((24, 24, 24, 8), 8, B.MIXED) > B.workspace_bytes((24, 24, 24, 8), 8)
     assert B.lib().subsurf4d_status_string(-3) == b"workspace too small"
+
+
+def test_batch_queries():
+    from paper_2111_11866_amd import binding as B
+
+    assert B.batch_workspace_bytes((40, 40, 40, 5), 5) > 0
+    # batched jobs are windows: at most 2^25 padded cells
+    assert B.batch_workspace_bytes((254, 254, 126, 1), 0) > 0          # 256 x 256 x 128 x 3 = 25.2 M padded
+    assert B.batch_workspace_bytes((254, 254, 254, 1), 0) == 0         # 256^3 x 3 = 50.3 M padded
+
+    assert B.batch_table_bytes(2048) > B.batch_table_bytes(1) > 0
+
+
+def test_index_division_multipliers():
+    """The batched kernels divide cell indices n < 2^31 by extents d < 2^17
+    with M = ceil(2^63/d) and q = floor(n*M / 2^63) (high product words).
+    Exact integer arithmetic here confirms the floor is exact over the range."""
+    import random
+
+    rnd = random.Random(11)
+    ds = [1, 2, 3, 5, 7, 12, 13, 17, 31, 32, 33, 47, 64, 65, 97, 98, 127, 128, 129, 255, 65536, 65537, 65538]
+    ds += [rnd.randrange(1, 1 << 17) for _ in range(200)]
+    for d in ds:
+        M = ((1 << 63) + d - 1) // d
+        assert M < (1 << 64)
+        ns = [0, 1, d - 1, d, d + 1, 2 * d - 1, (1 << 31) - 1, (1 << 31) - 1 - ((1 << 31) - 1) % d,
+              ((1 << 31) - 1) // d * d - 1]
+        ns += [rnd.randrange(0, 1 << 31) for _ in range(300)]
+        for n in ns:
+            if n < 0:
+                continue
+            # the device form: lo = n*M_lo, mid = n*M_hi + (lo >> 32), q = mid >> 31
+            lo = n * (M & 0xFFFFFFFF)
+            mid = n * (M >> 32) + (lo >> 32)
+            assert mid < (1 << 64)
+            assert (mid >> 31) == n // d, (n, d)
