@@ -118,10 +118,10 @@ __global__ __launch_bounds__(kBlock) void k_mx_sweep(MxArgs a)
     float* own = COLOR ? a.db : a.dr;
     const float* __restrict__ oth = COLOR ? a.dr : a.db;
     for (TileWalk tw(ncol); tw.t < tw.end; tw.t += tw.step) {
-        const int k = (int)(tw.t % L.n3) + 1;
-        const int64_t t2 = tw.t / L.n3;
-        const int jb = (int)(t2 % njb);
-        const int mt = (int)(t2 / njb);
+        const int mt = (int)(tw.t % ntm);                // slot-tile fastest, then k (as the FP64 sweep)
+        const int64_t t2 = tw.t / ntm;
+        const int k = (int)(t2 % L.n3) + 1;
+        const int jb = (int)(t2 / L.n3);
         const int j = jb * 4 + ty + 1;
         const int m = mt * 64 + tx;
         const bool jok = j <= L.n2;
@@ -231,7 +231,8 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
     const int grid_rows = grid_for(row_tiles, 1);
     const int64_t ncol = (int64_t)((L.half + 63) >> 6) * ((L.n2 + 3) >> 2) * L.n3;
     const int res_g = resident_grid(reinterpret_cast<const void*>(&k_mx_sweep<0>));
-    const int grid_cols = (int)(((ncol < res_g ? ncol : res_g) + kXcd - 1) / kXcd * kXcd);
+    const int half_res = res_g / 2;
+    const int grid_cols = (int)(((ncol < half_res ? ncol : half_res) + kXcd - 1) / kXcd * kXcd);
 
     Ctrl hc;
     SS4_HIP(hipMemcpyAsync(&hc, C, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
