@@ -15,7 +15,20 @@ HBM before the timed region; the per-job preparation runs before it.
 value = SOR voxel-updates/s over the timed steps (iterations x interior cells
 per step, divided by the wall time of the steps).  roofline: the red-black
 sweep kernel, 96 algorithmic bytes per voxel-update, timed with HIP events on
-the library's stream.
+the library's stream; traffic from the committed rocprofv3 counter summary
+when it was taken on the current kernel sources.
+
+The same JSON line also carries:
+* mixed: the same job with the mixed-precision solve (FP32 sweeps on BF16
+  coefficients in FP64 refinement) at the FP64 stopping rule and at 1e-10;
+* cpu_baseline: the oracle's red-black SOR on the host cores, on a bounded
+  crop of the same volume;
+* batched_windows: 2048 uneven windows (x,y,z in 24..64, t in 3..9) of 20
+  steps each, batched preparation + batched mixed-precision steps, against
+  plain per-job FP64 preparation and steps on a sample of the same jobs;
+* serving: a Poisson stream of lognormal windows served by continuous
+  batching against first-come-first-served plain FP64 jobs (jobs/s, p50/p99
+  latency from arrival to the result on the host).
 """
 from __future__ import annotations
 
