@@ -73,3 +73,15 @@ def test_index_division_multipliers():
             mid = n * (M >> 32) + (lo >> 32)
             assert mid < (1 << 64)
             assert (mid >> 31) == n // d, (n, d)
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """No fallback: without the built library every entry point raises."""
+    from paper_2111_11866_amd import binding as B
+
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(B, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        B.workspace_bytes((8, 8, 8, 2))
+    with pytest.raises(RuntimeError, match="missing"):
+        B.version()
