@@ -311,7 +311,8 @@ def main():
         "hbm_frac_sweeps": achieved / HBM_PEAK_GBS,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "red-black half-sweep (k_sweep_tm, red and black)",
+                     "kernel": "red-black half-sweep (%s, red and black)" %
+                               ("k_sweep_t2" if n[0] // 2 >= 64 else "k_sweep_tm"),
                      "avg_launch_ms": launch_ms, "launches": tm["sweep_launches"],
                      "bytes_per_launch": bytes_per_launch},
         "sweep_share_of_step_time": tm["sweep_ms"] / (dt * 1e3),

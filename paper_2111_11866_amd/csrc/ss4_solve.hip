@@ -456,9 +456,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tm(SweepArgs a)
 // Half-sweep, frame-marching with two cells per lane (rows of >= 64 slots,
 // whose u rows are 128-byte aligned): a wave covers one 128-slot coefficient
 // tile of one row, lane t owns slots m = 2t, 2t+1, and every stream moves 16
-// bytes per lane.  One block per column tile (128 slots x 4 y-rows at one z),
-// marching over the frames; blocks are mapped so that each XCD processes a
-// contiguous, k-fastest range of column tiles (shared z neighbours in L2).
+// bytes per lane.  A block walks column tiles (128 slots x 4 y-rows at one z),
+// marching over the frames of each; tiles are dealt as for k_sweep_tm.
 template <int COLOR>
 __global__ __launch_bounds__(kBlock) void k_sweep_t2(SweepArgs a)
 {
@@ -470,19 +469,17 @@ __global__ __launch_bounds__(kBlock) void k_sweep_t2(SweepArgs a)
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int njb = (L.n2 + 3) >> 2;
     const int64_t ncol = (int64_t)L.ntm * njb * L.n3;
-    const int64_t per_xcd = (ncol + kXcd - 1) / kXcd;
-    const int64_t t = (int64_t)(blockIdx.x % kXcd) * per_xcd + blockIdx.x / kXcd;
     const int64_t sy = L.rs, sz = (int64_t)L.p2 * L.rs, st = (int64_t)L.p2 * L.p3 * L.rs;
     const int64_t cst = (int64_t)L.n2 * L.n3 * L.ntm * kTileVals;
     const int last_slot = L.n1 >> 1;
     const double om = a.omega, om1 = 1.0 - a.omega;
     const double* __restrict__ uo = a.uoth;
     double acc = 0.0;
-    if (t < ncol) {
-        const int k = (int)(t % L.n3) + 1;
-        const int64_t t2 = t / L.n3;
-        const int jb = (int)(t2 % njb);
-        const int mt = (int)(t2 / njb);
+    for (TileWalk tw(ncol); tw.t < tw.end; tw.t += tw.step) {
+        const int mt = (int)(tw.t % L.ntm);              // slot-tile fastest, then k (as k_sweep_tm)
+        const int64_t t2 = tw.t / L.ntm;
+        const int k = (int)(t2 % L.n3) + 1;
+        const int jb = (int)(t2 / L.n3);
         const int j = jb * 4 + ty + 1;
         const int m = mt * kTileSlots + 2 * tx;
         const bool jok = j <= L.n2;                      // uniform across the wave
@@ -596,8 +593,10 @@ int sweep_grid(const Layout& L, int variant)
     int64_t work;
     int res;
     if (variant == 2) {
-        const int64_t ncol = (int64_t)L.ntm * ((L.n2 + 3) >> 2) * L.n3;
-        return (int)((ncol + kXcd - 1) / kXcd * kXcd);
+        work = (int64_t)L.ntm * ((L.n2 + 3) >> 2) * L.n3;
+        res = resident_grid(reinterpret_cast<const void*>(&k_sweep_t2<0>)) / 2;
+        const int64_t g = work < res ? work : res;
+        return (int)((g + kXcd - 1) / kXcd * kXcd);
     }
     if (variant == 1) {
         // half the resident size: fewer streams in flight per XCD keep DRAM
@@ -613,17 +612,19 @@ int sweep_grid(const Layout& L, int variant)
     return (int)((g + kXcd - 1) / kXcd * kXcd);
 }
 
-// Sweep kernel choice.  1 (default): frame-marching columns (k_sweep_tm), the
-// fastest measured on the config-2 volume; 0: row tiles (k_sweep); 2: marching
-// with two cells per lane (k_sweep_t2, wide rows only).  SUBSURF4D_SWEEP=r|t|p
-// selects one explicitly (all three give the same iterates).
+// Sweep kernel choice.  2 (default for rows of >= 64 slots): frame-marching
+// with two cells per lane and 16-byte accesses (k_sweep_t2), the fastest
+// measured on the 512x512x96x16 volume (3.95 ms vs 4.22 ms per half-sweep);
+// 1 (default for narrower rows): frame-marching, one cell per lane
+// (k_sweep_tm); 0: row tiles (k_sweep).  SUBSURF4D_SWEEP=r|t|p selects one
+// explicitly (all three give the same iterates).
 int sweep_variant(const Layout& L)
 {
     const bool wide = L.half >= 64;   // 128-byte aligned u rows, pairs stay in the row
     static const char* env = getenv("SUBSURF4D_SWEEP");
     if (env && env[0] == 'r') return 0;
-    if (env && env[0] == 'p' && wide) return 2;
-    return 1;
+    if (env && env[0] == 't') return 1;
+    return wide ? 2 : 1;
 }
 
 void fill_result(const Ctrl& hc, subsurf4d_result* res)
