@@ -68,7 +68,7 @@ def test_mixed_steps_cfg1(cfg1):
         print(row)
 
 
-@pytest.mark.parametrize("n", [(5, 4, 3, 3), (7, 6, 5, 4), (33, 9, 7, 3), (130, 5, 3, 3)])
+@pytest.mark.parametrize("n", [(5, 4, 3, 3), (7, 6, 5, 4), (33, 9, 7, 3), (130, 5, 3, 3), (129, 6, 4, 3), (257, 4, 3, 2)])
 def test_mixed_solve_ragged(n):
     rng = np.random.default_rng(sum(n))
     G = rng.uniform(0.05, 1, size=(4,) + B.padded_shape(n))
