@@ -107,8 +107,14 @@ def cpu_baseline(img, pp, sp, seconds):
     t0 = time.perf_counter()
     orc.sor(n, coef, b, w, sp.omega, 0.0, iters, orc.RB)
     dt = time.perf_counter() - t0
+    host = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            host = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": iters * cells / dt, "unit": "voxel-updates/s", "cores": orc.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "host_cpu": host,
             "sample": f"config-2 crop 128x128x96x4 ({cells} cells), one step's system, {iters} red-black "
                       f"iterations incl. the oracle's per-iteration residual, {dt:.1f} s"}
 
@@ -194,17 +200,24 @@ def bench_serving(rates, count, plain_seconds, log=None):
 
     from paper_2111_11866_amd import serve as S
 
+    import numpy as np
+
     pp, plain, mixed = S.default_params()
     out = {}
     for rate in rates:
         wins = S.make_windows(rate, count)
         bs = S.BatchServer(pp, mixed, steps=20, hbm_budget=96 << 30).run(wins)
+        got = {w.jid: w.result for w in wins if w.result is not None}
         del wins
         torch.cuda.empty_cache()
         wins = S.make_windows(rate, count)
         ps = S.PlainServer(pp, plain, steps=20).run(wins, max_seconds=plain_seconds)
-        del wins
+        errs = [float(np.abs(got[w.jid] - w.result).max() / max(np.abs(w.result).max(), 1e-300))
+                for w in wins if w.result is not None and w.jid in got]
+        del wins, got
         torch.cuda.empty_cache()
+        bs["max_rel_err_vs_plain_fp64"] = max(errs) if errs else None
+        bs["jobs_compared_with_plain"] = len(errs)
         out[str(rate)] = {"batched": bs, "plain_fp64": ps}
         if log:
             log(f"[serve] rate {rate}/s: batched {bs['jobs_per_s']:.1f} jobs/s p50 {bs['p50_latency_s']:.3f}s "
@@ -309,6 +322,7 @@ def main():
                    "grid": list(n), "cells": cells, "parallelism": "single GPU"},
         "iterations_per_step": iters,
         "hbm_frac_sweeps": achieved / HBM_PEAK_GBS,
+        "voxel_updates_per_s_kernel_time": updates / (tm["sweep_ms"] * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "red-black half-sweep (%s, red and black)" %
@@ -355,6 +369,24 @@ def main():
             }
             log(f"[bench] mixed {tol_name}: {mdt * 1e3 / mixed_steps:.1f} ms/step, passes "
                 f"{[r['outer'] for r in recs]}, inner sweep {mbytes / (mlaunch * 1e-3) / 1e9:.0f} GB/s")
+            # untimed: the error of each mixed step against the FP64 step from the same
+            # u^{resc;n-1} (max-abs and L2, relative to the FP64 result)
+            job.init(v=1.0, R=8.0, ball_r=sp.ball_r)
+            e_max, e_l2 = [], []
+            for _ in range(mixed_steps):
+                u_start = job.u.clone()
+                job.step(sp)
+                u64 = job.u.clone()
+                job.u.copy_(u_start)
+                job.step(msp)
+                d = job.u - u64
+                e_max.append(float(d.abs().max() / u64.abs().max()))
+                e_l2.append(float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(u64)))
+                job.u.copy_(u64)
+                del u_start, u64, d
+            out["mixed"][tol_name]["max_abs_rel_err_vs_fp64_per_step"] = e_max
+            out["mixed"][tol_name]["l2_rel_err_vs_fp64_per_step"] = e_l2
+            log(f"[bench] mixed {tol_name}: per-step max-abs rel err vs FP64 {max(e_max):.2e}")
     # practical HBM bandwidth of a plain 16-byte copy (4 GiB read + 4 GiB written)
     nb = 1 << 32
     src = torch.empty(nb, dtype=torch.uint8, device="cuda")
