@@ -24,8 +24,10 @@
  *    frame l-1; centres use the same coordinates.
  *  - Every pointer argument named "device" is device memory on the current
  *    HIP device; every other pointer is host memory.  The caller owns all
- *    memory.  The library never allocates or frees device memory in these
- *    calls; scratch space comes from the caller's workspace.
+ *    memory.  The library calls no hipMalloc/hipFree: scratch space comes
+ *    from the caller's workspace.  (The batched calls instantiate a HIP graph
+ *    per call, and on the legacy default stream run on one library-owned
+ *    non-blocking stream per device.)
  *  - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
  *    it.  Calls that iterate to a tolerance (prepare, step, solve) read the
  *    device-side convergence state between chunks of iterations and therefore
@@ -96,7 +98,7 @@ typedef struct {
     double omega;         /* SOR relaxation, in (0,2) */
     double tol;           /* stop at ||b - A u||_2 <= tol ||b||_2 (relative L2) */
     int32_t max_iter;     /* iteration cap (>= 1) */
-    int32_t check_every;  /* test the stopping rule every this many iterations (>= 1) */
+    int32_t check_every;  /* test the stopping rule every this many iterations (0 means 1) */
     int32_t rescale;      /* 1: local rescaling after the solve (needs owner/centres) */
     int32_t precision;    /* SUBSURF4D_FP64 or SUBSURF4D_MIXED */
     double ball_r;        /* ball radius of the local rescaling */
