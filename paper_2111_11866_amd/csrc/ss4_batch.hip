@@ -117,8 +117,8 @@ __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
                     double c[8];
 #pragma unroll
                     for (int d = 0; d < 4; ++d) {
-                        c[2 * d] = scale * G[(uint32_t)d * npad + p - sd[d]] / sqrt(J.eps2 + q[2 * d]);
-                        c[2 * d + 1] = scale * G[(uint32_t)d * npad + p] / sqrt(J.eps2 + q[2 * d + 1]);
+                        c[2 * d] = scale * G[(uint32_t)d * npad + p - sd[d]] * rsqrt(J.eps2 + q[2 * d]);
+                        c[2 * d + 1] = scale * G[(uint32_t)d * npad + p] * rsqrt(J.eps2 + q[2 * d + 1]);
                     }
                     double D = 1.0, bfull = w0, off = 0.0;
 #pragma unroll
