@@ -29,6 +29,10 @@ The same JSON line also carries:
 * serving: a Poisson stream of lognormal windows served by continuous
   batching against first-come-first-served plain FP64 jobs (jobs/s, p50/p99
   latency from arrival to the result on the host).
+Both window sections report each form's largest relative error (max-abs over
+a window / max |u|) against the converged solution of the same job (FP64 SOR
+to relative residual 1e-12, untimed); each form runs at its fastest setting
+that keeps this error within 1e-6.
 """
 from __future__ import annotations
 
@@ -161,21 +165,28 @@ def bench_batch(n_windows, steps, plain_sample, log_steps=False):
     for w in wins[plain_sample:]:
         w.state = None
     torch.cuda.empty_cache()
+    def run_plain(sp):
+        out = []
+        for q in range(plain_sample):
+            im = imgs[q]
+            job = B.Job(im.n, im.image, im.centres, im.seeds, precision=B.FP64)
+            job.prepare(pp)
+            job.init(v=1.0, R=0.0, ball_r=sp.ball_r)
+            for _ in range(steps):
+                job.step(sp)
+            out.append(job.u.cpu().numpy())
+            del job
+        return out
+
     t0 = time.perf_counter()
-    errs = []
-    for q in range(plain_sample):
-        im = imgs[q]
-        job = B.Job(im.n, im.image, im.centres, im.seeds, precision=B.FP64)
-        job.prepare(pp)
-        job.init(v=1.0, R=0.0, ball_r=plain.ball_r)
-        for _ in range(steps):
-            job.step(plain)
-        ref = job.u.cpu().numpy()
-        errs.append(float(np.abs(ref - batched_u[q]).max() / max(np.abs(ref).max(), 1e-300)))
-        del job
+    plain_u = run_plain(plain)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     plain_per_job = t_plain / plain_sample
+    conv_u = run_plain(S.converged_params(plain))      # untimed reference
+
+    def rel(a, ref):
+        return max(float(np.abs(x - r).max() / max(np.abs(r).max(), 1e-300)) for x, r in zip(a, ref))
     return {
         "windows": n_windows, "cells": cells, "steps_per_job": steps,
         "batched_jobs_per_s": n_windows / t_batch,
@@ -186,14 +197,16 @@ def bench_batch(n_windows, steps, plain_sample, log_steps=False):
         "plain_fp64_jobs_per_s": 1.0 / plain_per_job,
         "plain_sample_jobs": plain_sample,
         "speedup_jobs_per_s": (n_windows / t_batch) * plain_per_job,
-        "max_rel_err_batched_vs_plain_fp64": max(errs),
+        "max_rel_err_batched_vs_plain_fp64": rel(batched_u, plain_u),
+        "max_rel_err_vs_converged": {"batched": rel(batched_u, conv_u), "plain_fp64": rel(plain_u, conv_u),
+                                     "reference": "plain FP64 SOR to relative residual 1e-12, sample jobs"},
         "note": "both forms include preparation (thresholding, presmoothing, G, initial function and "
                 "rescale): one batched call for all windows, or one per job; device memory is allocated "
                 "outside the timed region in the batched form and inside it in the plain form",
     }
 
 
-def bench_serving(rates, count, plain_seconds, log=None):
+def bench_serving(rates, count, plain_seconds, log=None, ref_jobs=400):
     """Config 5: Poisson arrivals of lognormal-size windows; continuous batching
     against first-come-first-served plain FP64 per-job solves."""
     import torch
@@ -214,10 +227,27 @@ def bench_serving(rates, count, plain_seconds, log=None):
         ps = S.PlainServer(pp, plain, steps=20).run(wins, max_seconds=plain_seconds)
         errs = [float(np.abs(got[w.jid] - w.result).max() / max(np.abs(w.result).max(), 1e-300))
                 for w in wins if w.result is not None and w.jid in got]
-        del wins, got
+        plain_res = {w.jid: w.result for w in wins if w.result is not None}
+        del wins
         torch.cuda.empty_cache()
         bs["max_rel_err_vs_plain_fp64"] = max(errs) if errs else None
         bs["jobs_compared_with_plain"] = len(errs)
+        # converged reference for the first `ref_jobs` jobs (untimed, arrivals ignored)
+        ref = [w for w in S.make_windows(rate, count) if w.jid < ref_jobs]
+        S.PlainServer(pp, S.converged_params(plain), steps=20).run(ref, realtime=False)
+
+        def rel(res):
+            e = [float(np.abs(res[w.jid] - w.result).max() / max(np.abs(w.result).max(), 1e-300))
+                 for w in ref if w.jid in res]
+            return (max(e) if e else None), len(e)
+
+        (eb, nb), (ep, npl) = rel(got), rel(plain_res)
+        del ref, got, plain_res
+        torch.cuda.empty_cache()
+        bs["max_rel_err_vs_converged"] = eb
+        bs["jobs_compared_with_converged"] = nb
+        ps["max_rel_err_vs_converged"] = ep
+        ps["jobs_compared_with_converged"] = npl
         out[str(rate)] = {"batched": bs, "plain_fp64": ps}
         if log:
             log(f"[serve] rate {rate}/s: batched {bs['jobs_per_s']:.1f} jobs/s p50 {bs['p50_latency_s']:.3f}s "

@@ -213,7 +213,24 @@ def make_windows(rate, count, first_job=0, seed=7):
 
 
 def default_params():
+    """Parameters of the window jobs (eps = 1e-3, tau = 0.5, 20 steps).  Each
+    form runs at the fastest (omega, tolerance) whose results over a 20-step
+    job stay within 1e-6 relative (max-abs over the window / max |u|) of the
+    converged solution (converged_params), measured on 400 serving windows:
+
+    * plain FP64 SOR: omega = 1.35, relative residual 5e-9 (max error 5.3e-7;
+      omega = 1.3 at 1e-8 is faster per step but reaches 1.6e-6);
+    * mixed precision: omega relaxes only the FP32 sweeps of the correction
+      equation, the FP64 residual and refine_tol decide the result; 6 sweeps
+      per refinement pass at omega = 1.35, refine_tol 1e-8 (max error 5.1e-7,
+      about 3 passes per step)."""
     pp = B.PrepareParams(image_scale=1.0 / 255.0)
-    plain = B.StepParams(eps=1e-3, tau=0.5, omega=1.5, tol=1e-8)
-    mixed = replace(plain, precision=B.MIXED, refine_tol=1e-8, inner_sweeps=8)
+    plain = B.StepParams(eps=1e-3, tau=0.5, omega=1.35, tol=5e-9)
+    mixed = replace(plain, precision=B.MIXED, omega=1.35, refine_tol=1e-8, inner_sweeps=6)
     return pp, plain, mixed
+
+
+def converged_params(plain):
+    """The same step solved by FP64 SOR to relative residual 1e-12: the
+    reference the window results are measured against."""
+    return replace(plain, tol=1e-12, max_iter=100000)

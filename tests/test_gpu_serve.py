@@ -38,3 +38,21 @@ def test_serving_budget_makes_jobs_wait_none_dropped():
     two = sorted(S.window_bytes(w.img.n, len(w.img.centres)) for w in wins)[:2]
     stats = S.BatchServer(pp, mixed, steps=2, hbm_budget=sum(two) + 1).run(S.make_windows(5000.0, 16))
     assert stats["jobs"] == 16 and stats["max_concurrent"] <= 2
+
+
+def test_window_forms_within_1e6_of_converged():
+    """20-step window jobs: the batched mixed form and the plain FP64 form at
+    their default settings both stay within 1e-6 relative of the converged
+    solution (FP64 SOR to relative residual 1e-12)."""
+    pp, plain, mixed = S.default_params()
+    res = {}
+    for name, srv in (("batched", S.BatchServer(pp, mixed, steps=20, hbm_budget=8 << 30)),
+                      ("plain", S.PlainServer(pp, plain, steps=20)),
+                      ("converged", S.PlainServer(pp, S.converged_params(plain), steps=20))):
+        wins = S.make_windows(1000.0, 12)
+        srv.run(wins, realtime=False)
+        res[name] = [w.result for w in wins]
+    for form in ("batched", "plain"):
+        for q, (a, r) in enumerate(zip(res[form], res["converged"])):
+            e = np.abs(a - r).max() / np.abs(r).max()
+            assert e <= 1e-6, (form, q, e)
