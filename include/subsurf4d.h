@@ -95,7 +95,8 @@ typedef struct {
 typedef struct {
     double eps;           /* regularisation epsilon of A_eps (> 0) */
     double tau;           /* time step (>= 0; 0 gives the identity solve) */
-    double omega;         /* SOR relaxation, in (0,2) */
+    double omega;         /* SOR relaxation, in (0,2); MIXED: relaxation of the inner FP32
+                             sweeps only (the FP64 residual and refine_tol decide the result) */
     double tol;           /* stop at ||b - A u||_2 <= tol ||b||_2 (relative L2) */
     int32_t max_iter;     /* iteration cap (>= 1) */
     int32_t check_every;  /* test the stopping rule every this many iterations (0 means 1) */
