@@ -295,6 +295,8 @@ size_t subsurf4d_batch_table_bytes(int32_t n_jobs);
  * array of n_jobs, may be NULL), table (device, >= subsurf4d_batch_table_bytes).
  * Synchronises `stream`.  Returns SUBSURF4D_NOT_CONVERGED if any job hit its
  * cap, SUBSURF4D_ENONFINITE if any job failed (see each job's result).
+ * n_jobs = 0 is an empty batch: SUBSURF4D_OK, nothing enqueued (jobs and
+ * table may then be NULL).
  */
 int subsurf4d_step_batched(const subsurf4d_batch_job* jobs, int32_t n_jobs, const subsurf4d_step_params* params,
                            subsurf4d_result* results, void* table, size_t table_bytes, void* stream);
@@ -332,6 +334,7 @@ typedef struct {
  * SUBSURF4D_ENONFINITE), table (device, >= subsurf4d_batch_table_bytes(n_jobs),
  * 256-byte aligned).  Synchronises `stream`.  Returns 0,
  * SUBSURF4D_NOT_CONVERGED if any job's solve hit its cap, or a negative code.
+ * n_jobs = 0 is an empty batch: SUBSURF4D_OK, nothing enqueued.
  */
 int subsurf4d_prepare_batched(const subsurf4d_batch_prepare_job* jobs, int32_t n_jobs,
                               const subsurf4d_prepare_params* params, double v, double R, double ball_r,

@@ -321,7 +321,7 @@ def step_batched(jobs, params: StepParams, table, stream=None):
                            _p(j.bws), j.bws.numel())
     res = (Result * len(jobs))()
     rc = _check(lib().subsurf4d_step_batched(arr, len(jobs), ctypes.byref(params.c()), res, _p(table),
-                                              table.numel(), _stream(stream)))
+                                              0 if table is None else table.numel(), _stream(stream)))
     return rc, [r.as_dict() for r in res]
 
 
@@ -337,7 +337,8 @@ def prepare_batched(jobs, pp: PrepareParams, v, R, ball_r, table, stream=None):
                                   _p(j.seeds), _p(j.G), _p(j.owner), _p(j.u), _p(j.bws), j.bws.numel())
     st = (ctypes.c_int32 * len(jobs))()
     rc = _check(lib().subsurf4d_prepare_batched(arr, len(jobs), ctypes.byref(pp.c()), float(v), float(R),
-                                                 float(ball_r), st, _p(table), table.numel(), _stream(stream)))
+                                                 float(ball_r), st, _p(table),
+                                                 0 if table is None else table.numel(), _stream(stream)))
     return rc, list(st)
 
 

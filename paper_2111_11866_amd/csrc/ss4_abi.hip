@@ -391,8 +391,9 @@ int subsurf4d_step_batched(const subsurf4d_batch_job* jobs, int32_t n_jobs, cons
 {
     SS4_GUARD_BEGIN
     g_error.clear();
-    if (!jobs || n_jobs < 1 || !table) return fail(SUBSURF4D_EINVAL, "bad batch arguments");
     if (int rc = check_step_params(params)) return rc;
+    if (n_jobs == 0) return SUBSURF4D_OK;
+    if (!jobs || n_jobs < 0 || !table) return fail(SUBSURF4D_EINVAL, "bad batch arguments");
     if (params->precision != SUBSURF4D_MIXED) return fail(SUBSURF4D_EINVAL, "the batched step is mixed precision");
     if (reinterpret_cast<uintptr_t>(table) % 256 != 0) return fail(SUBSURF4D_EINVAL, "table must be 256-byte aligned");
     for (int q = 0; q < n_jobs; ++q) {
@@ -414,8 +415,9 @@ int subsurf4d_prepare_batched(const subsurf4d_batch_prepare_job* jobs, int32_t n
 {
     SS4_GUARD_BEGIN
     g_error.clear();
-    if (!jobs || n_jobs < 1 || !table) return fail(SUBSURF4D_EINVAL, "bad batch arguments");
     if (int rc = check_prepare_params(params)) return rc;
+    if (n_jobs == 0) return SUBSURF4D_OK;
+    if (!jobs || n_jobs < 0 || !table) return fail(SUBSURF4D_EINVAL, "bad batch arguments");
     if (!(v > 0.0) || !std::isfinite(v)) return fail(SUBSURF4D_EINVAL, "v must be positive");
     if (!std::isfinite(R) || R > 1e6) return fail(SUBSURF4D_EINVAL, "R out of range");
     if (!std::isfinite(ball_r) || ball_r > 1e6) return fail(SUBSURF4D_EINVAL, "ball_r out of range");

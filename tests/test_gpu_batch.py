@@ -143,3 +143,72 @@ def test_batched_tau_zero_and_not_converged():
         assert np.array_equal(H(j.u), b)
     rc, res = run(jobs, replace(SP, refine_tol=1e-16, inner_sweeps=2, max_iter=4))
     assert rc == B.NOT_CONVERGED and all(r["status"] == B.NOT_CONVERGED for r in res)
+
+
+def test_empty_batch():
+    """No jobs: both batched calls return OK and enqueue nothing."""
+    assert B.step_batched([], SP, None) == (0, [])
+    assert B.prepare_batched([], PP, 1.0, 0.0, 8.0, None) == (0, [])
+
+
+def raw_job(n, rng):
+    """A batched job on random coefficients (G in [0.05, 1]) and a random
+    level with zero Dirichlet ghosts, no balls (no rescale)."""
+    from types import SimpleNamespace
+
+    G = rng.uniform(0.05, 1.0, size=(4,) + B.padded_shape(n))
+    w = np.zeros(B.padded_shape(n))
+    w[1:-1, 1:-1, 1:-1, 1:-1] = rng.uniform(0.0, 1.0, size=tuple(reversed(n)))
+    dev = lambda a: torch.from_numpy(a).to("cuda")  # noqa: E731
+    bws = torch.empty(B.batch_workspace_bytes(n, 0), dtype=torch.uint8, device="cuda")
+    return SimpleNamespace(n=n, h=1.0, G=dev(G), u=dev(w), owner=None, centres=None, nc=0, bws=bws), G, w
+
+
+def test_batched_degenerate_windows_against_oracle():
+    """Windows with one or two cells along some axes (rows of one slot, a
+    single frame, a single cell) in one batch, each against the FP64 oracle
+    converged to 1e-14."""
+    from dataclasses import replace
+
+    rng = np.random.default_rng(31)
+    sizes = [(1, 1, 1, 1), (2, 1, 1, 1), (1, 3, 1, 2), (3, 2, 2, 1), (5, 1, 4, 2), (1, 1, 1, 7), (130, 1, 1, 1),
+             (2, 2, 2, 2)]
+    made = [raw_job(n, rng) for n in sizes]
+    sp = replace(SP, rescale=False)
+    rc, res = run([m[0] for m in made], sp)
+    assert rc == 0
+    for (j, G, w), r in zip(made, res):
+        assert r["status"] == 0, (j.n, r)
+        ref = orc.step(j.n, G, w, None, None, orc.StepParams(tol=1e-14, rescale=False), orc.RB)["u_resc"]
+        err = np.abs(H(j.u) - ref).max()
+        assert err <= 1e-8 * max(np.abs(ref).max(), 1e-300), (j.n, err)
+
+
+def test_batched_window_at_the_size_limit():
+    """A window of 200x200x200x2 (32.97 M padded cells, 98% of the 2^25
+    limit of a batched job) next to a small one: every cell against the
+    single-job FP64 step solved to 1e-12 (itself checked against the oracle),
+    so the index decode and 32-bit offsets are exercised at their largest."""
+    from dataclasses import replace
+
+    rng = np.random.default_rng(37)
+    big, small = (200, 200, 200, 2), (5, 4, 3, 3)
+    assert np.prod([v + 2 for v in big]) <= 1 << 25
+    assert B.batch_workspace_bytes(big, 0) > 0
+    made = [raw_job(n, rng) for n in (big, small)]
+    refs = []
+    for j, G, w in made:
+        u = torch.from_numpy(w).to("cuda")
+        ws = B.alloc_workspace(j.n, 0, B.FP64)
+        r = B.step(j.n, 1.0, j.G, None, 0, None, u,
+                   B.StepParams(tol=1e-12, max_iter=100000, rescale=False), ws)
+        assert r["status"] == 0
+        refs.append(H(u))
+        del ws, u
+    rc, res = run([m[0] for m in made], replace(SP, rescale=False))
+    assert rc == 0 and all(r["status"] == 0 for r in res)
+    # refine_tol 1e-10 bounds ||r||_2 / ||b||_2; with ||A^-1||_inf <= 1 the
+    # max error of 16 M cells is bounded by 1e-10 ||b||_2 ~ 2e-7 at worst
+    for (j, _, _), ref in zip(made, refs):
+        err = np.abs(H(j.u) - ref).max()
+        assert err <= 1e-7 * np.abs(ref).max(), (j.n, err)
