@@ -392,7 +392,10 @@ def main():
             mt = B.timing(3)
             B.timing(0)
             mlaunch = mt["sweep_ms"] / max(mt["sweep_launches"], 1)
-            mbytes = 32.0 * cells / 2.0
+            # 32 B per update, except the first iteration of each pass, which
+            # starts from d = 0: red 8 B (r/D read, d written), black 28 B
+            m_in = args.inner
+            mbytes = cells / 2.0 * (64.0 * m_in - 28.0) / (2.0 * m_in)
             out.setdefault("mixed", {})[tol_name] = {
                 "ms_per_step": mdt * 1e3 / mixed_steps,
                 "speedup_vs_fp64_step": (dt / args.steps) / (mdt / mixed_steps),
@@ -403,6 +406,7 @@ def main():
                 "inner_sweep_avg_launch_ms": mlaunch,
                 "inner_sweep_GBs_algorithmic": mbytes / (mlaunch * 1e-3) / 1e9,
                 "inner_bytes_per_update": 32,
+                "inner_bytes_per_launch_avg": mbytes,
             }
             log(f"[bench] mixed {tol_name}: {mdt * 1e3 / mixed_steps:.1f} ms/step, passes "
                 f"{[r['outer'] for r in recs]}, inner sweep {mbytes / (mlaunch * 1e-3) / 1e9:.0f} GB/s")

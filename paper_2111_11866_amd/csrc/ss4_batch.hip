@@ -259,9 +259,15 @@ __device__ __forceinline__ float sweep_cell(u32x4 cw, float s, float xl, float x
     return om * s + om1 * old;
 }
 
+// FIRST (both shapes): the first iteration of a refinement pass, which
+// starts from d = 0.  Its red half-sweep is d = omega*r/D (no coefficient or
+// neighbour reads) and its black half-sweep takes the old d as 0 without
+// reading it; both give the bits of the general form on a zero d, so no pass
+// needs d cleared beforehand.
+
 // FP32 half-sweep of colour COLOR, flat shape: a work item is 256
 // consecutive q of one colour.
-template <int COLOR>
+template <int COLOR, bool FIRST>
 __global__ __launch_bounds__(kBlock) void kb_sweep(BTable T)
 {
     const float om = T.omega, om1 = 1.0f - T.omega;
@@ -278,9 +284,13 @@ __global__ __launch_bounds__(kBlock) void kb_sweep(BTable T)
             Cell c;
             if (!bdecode(J, COLOR, q, c)) continue;
             const uint32_t ui = c.prow * J.rsu + 1 + c.m;
+            if constexpr (FIRST && COLOR == 0) {
+                own[ui] = om * rf[cb + q];
+                continue;
+            }
             own[ui] = sweep_cell(c16[cb + q], rf[cb + q], oth[ui - c.par], oth[ui + 1 - c.par], oth[ui - sy],
                                  oth[ui + sy], oth[ui - sz], oth[ui + sz], oth[ui - st], oth[ui + st], om, om1,
-                                 own[ui]);
+                                 FIRST ? 0.0f : own[ui]);
         }
     });
 }
@@ -291,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void kb_sweep(BTable T)
 // tile of 256 slots x N4 frames).  The other colour's values of the slot at
 // l-1, l, l+1 stay in registers: they are the cell's t-neighbours and one of
 // its x-neighbours.  Cell (j,k,l) of slot m has q = (l-1)*nqf + qf.
-template <int COLOR>
+template <int COLOR, bool FIRST>
 __global__ __launch_bounds__(kBlock) void kb_sweep_tm(BTable T)
 {
     const float om = T.omega, om1 = 1.0f - T.omega;
@@ -313,6 +323,14 @@ __global__ __launch_bounds__(kBlock) void kb_sweep_tm(BTable T)
             const int j = (int)(r - r2 * (uint32_t)J.n2) + 1;
             const int k = (int)r2 + 1;
             const uint32_t u0 = ((uint32_t)k * J.p2 + (uint32_t)j) * J.rsu + 1 + m;   // row (j,k,l=0)
+            if constexpr (FIRST && COLOR == 0) {
+                for (int l = 1; l <= J.n4; ++l) {
+                    const int par = (COLOR + j + k + l) & 1;
+                    const int cnt = par ? (J.n1 + 1) >> 1 : J.n1 >> 1;
+                    if (m < cnt) own[u0 + (uint32_t)l * st] = om * rf[cb + (uint32_t)(l - 1) * nqf + qf];
+                }
+                continue;
+            }
             float Bm = oth[u0];
             float Bc = oth[u0 + st];
             for (int l = 1; l <= J.n4; ++l) {
@@ -324,7 +342,8 @@ __global__ __launch_bounds__(kBlock) void kb_sweep_tm(BTable T)
                     const uint32_t q = (uint32_t)(l - 1) * nqf + qf;
                     const float xo = oth[par ? ui - 1 : ui + 1];
                     own[ui] = sweep_cell(c16[cb + q], rf[cb + q], par ? xo : Bc, par ? Bc : xo, oth[ui - sy],
-                                         oth[ui + sy], oth[ui - sz], oth[ui + sz], Bm, Bp, om, om1, own[ui]);
+                                         oth[ui + sy], oth[ui - sz], oth[ui + sz], Bm, Bp, om, om1,
+                                         FIRST ? 0.0f : own[ui]);
                 }
                 Bm = Bc;
                 Bc = Bp;
@@ -333,7 +352,7 @@ __global__ __launch_bounds__(kBlock) void kb_sweep_tm(BTable T)
     });
 }
 
-// x += d, d = 0 for unfinished jobs.
+// x += d for unfinished jobs (the next pass's first iteration does not read d).
 __global__ __launch_bounds__(kBlock) void kb_update(BTable T)
 {
     for_runs(T.act_both, T.act_jobs, *T.n_act, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
@@ -348,7 +367,6 @@ __global__ __launch_bounds__(kBlock) void kb_update(BTable T)
             SS4_GLOBAL double* x = gbl(colour ? J.xb : J.xr);
             SS4_GLOBAL float* d = gbl(colour ? J.db : J.dr);
             x[ui] += (double)d[ui];
-            d[ui] = 0.0f;
         }
     });
 }
@@ -680,19 +698,29 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
     // the corrections are zeroed again afterwards.  Flags can force a shape.
     int g_sw = 0, shape = 0;
     const int forced = (sp.flags & SUBSURF4D_FLAG_SWEEP_FLAT) ? 1 : (sp.flags & SUBSURF4D_FLAG_SWEEP_MARCH) ? 2 : 0;
-    auto sweep_pair = [&](int shp, int g) {
+    auto sweep_pair = [&](int shp, int g, bool first) {
         if (shp == 0) {
-            kb_sweep<0><<<g, kBlock, 0, s>>>(T);
-            kb_sweep<1><<<g, kBlock, 0, s>>>(T);
+            if (first) {
+                kb_sweep<0, true><<<g, kBlock, 0, s>>>(T);
+                kb_sweep<1, true><<<g, kBlock, 0, s>>>(T);
+            } else {
+                kb_sweep<0, false><<<g, kBlock, 0, s>>>(T);
+                kb_sweep<1, false><<<g, kBlock, 0, s>>>(T);
+            }
         } else {
-            kb_sweep_tm<0><<<g, kBlock, 0, s>>>(T);
-            kb_sweep_tm<1><<<g, kBlock, 0, s>>>(T);
+            if (first) {
+                kb_sweep_tm<0, true><<<g, kBlock, 0, s>>>(T);
+                kb_sweep_tm<1, true><<<g, kBlock, 0, s>>>(T);
+            } else {
+                kb_sweep_tm<0, false><<<g, kBlock, 0, s>>>(T);
+                kb_sweep_tm<1, false><<<g, kBlock, 0, s>>>(T);
+            }
         }
     };
     if (forced) {
         shape = forced - 1;
-        g_sw = shape == 0 ? resident_grid(reinterpret_cast<const void*>(&kb_sweep<0>))
-                          : resident_grid(reinterpret_cast<const void*>(&kb_sweep_tm<0>));
+        g_sw = shape == 0 ? resident_grid(reinterpret_cast<const void*>(&kb_sweep<0, false>))
+                          : resident_grid(reinterpret_cast<const void*>(&kb_sweep_tm<0, false>));
     } else {
         static std::mutex mu;
         static std::map<std::pair<int, int64_t>, std::pair<int, int>> tuned;
@@ -708,13 +736,13 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
             SS4_HIP(hipEventCreate(&e1));
             float best = 1e30f;
             for (int shp = 0; shp < 2; ++shp) {
-                const int res = shp == 0 ? resident_grid(reinterpret_cast<const void*>(&kb_sweep<0>))
-                                         : resident_grid(reinterpret_cast<const void*>(&kb_sweep_tm<0>));
+                const int res = shp == 0 ? resident_grid(reinterpret_cast<const void*>(&kb_sweep<0, false>))
+                                         : resident_grid(reinterpret_cast<const void*>(&kb_sweep_tm<0, false>));
                 for (int mult = 1; mult <= 4; mult *= 2) {
                     const int g = res * mult;
-                    sweep_pair(shp, g);
+                    sweep_pair(shp, g, false);
                     SS4_HIP(hipEventRecord(e0, s));
-                    for (int rep = 0; rep < 2; ++rep) sweep_pair(shp, g);
+                    for (int rep = 0; rep < 2; ++rep) sweep_pair(shp, g, false);
                     SS4_HIP(hipEventRecord(e1, s));
                     SS4_HIP(hipEventSynchronize(e1));
                     float ms = 0.f;
@@ -737,7 +765,7 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
     // graph and replayed until every job has finished
     const bool eager = (sp.flags & SUBSURF4D_FLAG_NO_GRAPH) != 0;
     auto enqueue_pass = [&]() {
-        for (int it = 0; it < m; ++it) sweep_pair(shape, g_sw);
+        for (int it = 0; it < m; ++it) sweep_pair(shape, g_sw, it == 0);
         kb_update<<<g_up, kBlock, 0, s>>>(T);
         kb_next_pass<<<1, 64, 0, s>>>(T);
         kb_residual<<<g_res, kBlock, 0, s>>>(T);

@@ -116,7 +116,12 @@ __device__ __forceinline__ float mx_cell(uint4 w, float rhs, float xl, float xr,
 
 // FP32 red-black half-sweep on the scaled correction system, frame-marching
 // form (as the FP64 sweep): d <- omega*(r/D + sum_f c'_f d_f) + (1-omega)*d.
-template <int COLOR>
+// FIRST: the first iteration of a refinement pass, which starts from d = 0.
+// Its red half-sweep is then d = omega*r/D (no coefficient or neighbour
+// reads) and its black half-sweep takes the old d as 0 without reading it;
+// both give the bits of the general form on a zero d, so no pass needs d
+// cleared beforehand.
+template <int COLOR, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_mx_sweep(MxArgs a)
 {
     const Layout& L = a.L;
@@ -140,6 +145,18 @@ __global__ __launch_bounds__(kBlock) void k_mx_sweep(MxArgs a)
         const bool sok = jok && m <= last_slot;
         const int64_t ub = ((int64_t)k * L.p2 + j) * L.rs + L.xoff + m;
         const int64_t rb = (int64_t)(k - 1) * L.n2 + (j - 1);
+        if constexpr (FIRST && COLOR == 0) {
+            if (!jok) continue;
+            for (int l = 1; l <= L.n4; ++l) {
+                const int par = (COLOR + j + k + l) & 1;
+                const int cnt = par ? (L.n1 + 1) >> 1 : L.n1 >> 1;
+                if (m < cnt) {
+                    const int64_t q = mrec(L, COLOR, rb + (int64_t)(l - 1) * L.n3 * L.n2, m);
+                    own[ub + (int64_t)l * st] = om * __builtin_nontemporal_load(a.rf + q);
+                }
+            }
+            continue;
+        }
         float Bm = sok ? oth[ub] : 0.0f;
         float Bc = sok ? oth[ub + st] : 0.0f;
         for (int l = 1; l <= L.n4; ++l) {
@@ -157,7 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_mx_sweep(MxArgs a)
                     const uint4 w = ld16_stream(a.c16 + q);
                     const float rhs = __builtin_nontemporal_load(a.rf + q);
                     own[ui] = mx_cell(w, rhs, par ? left : Bc, par ? Bc : right, oth[ui - sy], oth[ui + sy],
-                                      oth[ui - sz], oth[ui + sz], Bm, Bp, om, om1, own[ui]);
+                                      oth[ui - sz], oth[ui + sz], Bm, Bp, om, om1, FIRST ? 0.0f : own[ui]);
                 }
             }
             Bm = Bc;
@@ -166,7 +183,8 @@ __global__ __launch_bounds__(kBlock) void k_mx_sweep(MxArgs a)
     }
 }
 
-// x += d and d = 0 on every interior cell of both colours.
+// x += d on every interior cell of both colours (the next pass's first
+// iteration does not read d).
 __global__ __launch_bounds__(kBlock) void k_mx_update(MxArgs a)
 {
     const Layout& L = a.L;
@@ -193,7 +211,6 @@ __global__ __launch_bounds__(kBlock) void k_mx_update(MxArgs a)
         double* x = colour ? a.xb : a.xr;
         float* d = colour ? a.db : a.dr;
         x[ui] += (double)d[ui];
-        d[ui] = 0.0f;
     }
 }
 
@@ -238,7 +255,7 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
     const int64_t ncol = (int64_t)((L.half + 63) >> 6) * ((L.n2 + 3) >> 2) * L.n3;
     // one cell per lane: two cells per lane (as the FP64 sweep) measured slower
     // for the FP32 correction (3.36 vs 4.13 TB/s on the 512x512x96x16 volume)
-    const int res_g = resident_grid(reinterpret_cast<const void*>(&k_mx_sweep<0>)) / 2;
+    const int res_g = resident_grid(reinterpret_cast<const void*>(&k_mx_sweep<0, false>)) / 2;
     const int grid_cols = (int)(((ncol < res_g ? ncol : res_g) + kXcd - 1) / kXcd * kXcd);
 
     Ctrl hc;
@@ -254,9 +271,11 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
         SS4_HIP(hipStreamSynchronize(s));
         if (hc.done) break;
         timer.begin();
-        for (int it = 0; it < m; ++it) {
-            k_mx_sweep<0><<<grid_cols, kBlock, 0, s>>>(a);
-            k_mx_sweep<1><<<grid_cols, kBlock, 0, s>>>(a);
+        k_mx_sweep<0, true><<<grid_cols, kBlock, 0, s>>>(a);
+        k_mx_sweep<1, true><<<grid_cols, kBlock, 0, s>>>(a);
+        for (int it = 1; it < m; ++it) {
+            k_mx_sweep<0, false><<<grid_cols, kBlock, 0, s>>>(a);
+            k_mx_sweep<1, false><<<grid_cols, kBlock, 0, s>>>(a);
         }
         timer.end();
         k_mx_update<<<grid_rows, kBlock, 0, s>>>(a);
