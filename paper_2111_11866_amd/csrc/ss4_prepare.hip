@@ -399,8 +399,9 @@ int lhe_solve(const WsPlan& P, double a, double omega, double tol, int max_iter,
     double* pa = ws_ptr<double>(ws, P.part_a);
     double* pb = ws_ptr<double>(ws, P.part_b);
     const int gs = grid_for(L.nint);
-    // few blocks for the residual: each block ends with one device-scope fence
-    const int gr = grid_for(L.nint) < 256 ? grid_for(L.nint) : 256;
+    // the residual's per-block partials fit the workspace's partial arrays
+    // (at least kGridCap entries), so it takes the sweep's grid
+    const int gr = gs;
     k_copy_f64<<<grid_for(L.nint), kBlock, 0, s>>>(rhs, J, L.nint);
     k_ctrl_init<<<1, 64, 0, s>>>(C, tol, max_iter);
     k_lhe_residual<<<gr, kBlock, 0, s>>>(L, a, rhs, J, 0, pa, pb, C);
