@@ -78,11 +78,11 @@ typedef struct {
 /* Parameters of the per-job preparation (Sec. 3.1, Sec. 3.2.2 G equation). */
 typedef struct {
     double K;             /* edge-detector sensitivity, g(s) = 1/(1+K s^2), K >= 0 */
-    double delta;         /* weight of |grad I0_sigma| */
-    double vartheta;      /* weight of |grad ITH_sigma| */
+    double delta;         /* weight of |grad I0_sigma| (finite, >= 0) */
+    double vartheta;      /* weight of |grad ITH_sigma| (finite, >= 0) */
     double lambda;        /* threshold TH = lambda*alpha + (1-lambda)*beta, in [0,1] */
     double ball_r;        /* ball radius r (voxels) of the local thresholding */
-    double smooth_tau;    /* presmoothing: implicit heat-step size (>= 0) */
+    double smooth_tau;    /* presmoothing: implicit heat-step size (finite, >= 0) */
     int32_t smooth_steps; /* number of implicit heat steps (>= 0) */
     int32_t smooth_max_iter; /* SOR iteration cap of each heat step */
     double smooth_omega;  /* SOR relaxation of the heat steps, in (0,2); <= 0: Young's optimum

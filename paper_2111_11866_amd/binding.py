@@ -182,12 +182,33 @@ def _check(rc):
     return rc
 
 
-def _p(t):
-    """Device pointer of a torch tensor (or None)."""
+def _p(t, name="tensor", dtype=None, nbytes=0):
+    """Device pointer of a torch tensor (or None), after checking that the
+    library may use it: a contiguous CUDA tensor of the expected dtype (a
+    torch dtype name such as "float64") holding at least `nbytes` bytes.  The
+    library only sees the address, so a host tensor or a short buffer would
+    make a kernel fault; here it raises ValueError instead."""
     if t is None:
         return None
-    assert t.is_contiguous(), "tensors passed to the library must be contiguous"
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{name}: expected a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensors passed to the library must be contiguous")
+    if dtype is not None and str(t.dtype) != "torch." + dtype:
+        raise ValueError(f"{name}: expected torch.{dtype}, got {t.dtype}")
+    if _nb(t) < nbytes:
+        raise ValueError(f"{name}: {_nb(t)} bytes, the call needs {nbytes}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _nb(t):
+    """Byte size of a tensor (0 for None)."""
+    return 0 if t is None else t.numel() * t.element_size()
+
+
+def _cells(n):
+    """(interior, padded) cell counts of grid n."""
+    return int(np.prod(n)), int(np.prod([v + 2 for v in n]))
 
 
 def _stream(stream=None):
@@ -238,31 +259,49 @@ def prepare_g(n, h, image, centres, n_centres, params: PrepareParams, G, owner, 
     import torch
 
     dt = {torch.uint8: U8, torch.float32: F32, torch.float64: F64}[image.dtype]
-    return _check(lib().subsurf4d_prepare_g(ctypes.byref(grid(n, h)), _p(image), dt, _p(centres),
-                                             int(n_centres), ctypes.byref(params.c()), _p(G), _p(owner),
-                                             _p(ws), ws.numel(), _stream(stream)))
+    ni, npd = _cells(n)
+    return _check(lib().subsurf4d_prepare_g(ctypes.byref(grid(n, h)), _p(image, "image", None,
+                                                                          ni * image.element_size()), dt,
+                                             _p(centres, "centres", None, 16 * int(n_centres)),
+                                             int(n_centres), ctypes.byref(params.c()),
+                                             _p(G, "G", "float64", 32 * npd), _p(owner, "owner", "int32", 4 * ni),
+                                             _p(ws, "workspace"), _nb(ws), _stream(stream)))
 
 
 def init_u(n, h, seeds, n_seeds, v, R, u, stream=None):
-    return _check(lib().subsurf4d_init_u(ctypes.byref(grid(n, h)), _p(seeds), int(n_seeds), float(v),
-                                          float(R), _p(u), _stream(stream)))
+    ni, npd = _cells(n)
+    return _check(lib().subsurf4d_init_u(ctypes.byref(grid(n, h)), _p(seeds, "seeds", None, 16 * int(n_seeds)),
+                                          int(n_seeds), float(v), float(R), _p(u, "u", "float64", 8 * npd),
+                                          _stream(stream)))
 
 
 def rescale(n, h, centres, n_centres, ball_r, owner, u, ws, stream=None):
-    return _check(lib().subsurf4d_rescale(ctypes.byref(grid(n, h)), _p(centres), int(n_centres),
-                                           float(ball_r), _p(owner), _p(u), _p(ws), ws.numel(),
+    ni, npd = _cells(n)
+    return _check(lib().subsurf4d_rescale(ctypes.byref(grid(n, h)), _p(centres, "centres", None, 16 * int(n_centres)),
+                                           int(n_centres), float(ball_r), _p(owner, "owner", "int32", 4 * ni),
+                                           _p(u, "u", "float64", 8 * npd), _p(ws, "workspace"), _nb(ws),
                                            _stream(stream)))
 
 
 def assemble(n, h, G, u, params: StepParams, coef, b, stream=None):
-    return _check(lib().subsurf4d_assemble(ctypes.byref(grid(n, h)), _p(G), _p(u), ctypes.byref(params.c()),
-                                            _p(coef), _p(b), _stream(stream)))
+    ni, npd = _cells(n)
+    return _check(lib().subsurf4d_assemble(ctypes.byref(grid(n, h)), _p(G, "G", "float64", 32 * npd),
+                                            _p(u, "u", "float64", 8 * npd), ctypes.byref(params.c()),
+                                            _p(coef, "coef", "float64", 64 * ni), _p(b, "b", "float64", 8 * ni),
+                                            _stream(stream)))
+
+
+def _step_ptrs(n, G, centres, n_centres, owner, u):
+    ni, npd = _cells(n)
+    return (_p(G, "G", "float64", 32 * npd), _p(centres, "centres", None, 16 * int(n_centres)),
+            _p(owner, "owner", "int32", 4 * ni), _p(u, "u", "float64", 8 * npd))
 
 
 def step(n, h, G, centres, n_centres, owner, u, params: StepParams, ws, stream=None) -> dict:
     res = Result()
-    _check(lib().subsurf4d_step(ctypes.byref(grid(n, h)), _p(G), _p(centres), int(n_centres), _p(owner),
-                                _p(u), ctypes.byref(params.c()), ctypes.byref(res), _p(ws), ws.numel(),
+    pG, pc, po, pu = _step_ptrs(n, G, centres, n_centres, owner, u)
+    _check(lib().subsurf4d_step(ctypes.byref(grid(n, h)), pG, pc, int(n_centres), po, pu,
+                                ctypes.byref(params.c()), ctypes.byref(res), _p(ws, "workspace"), _nb(ws),
                                 _stream(stream)))
     return res.as_dict()
 
@@ -270,16 +309,21 @@ def step(n, h, G, centres, n_centres, owner, u, params: StepParams, ws, stream=N
 def step_dirichlet(n, h, G, ub, centres, n_centres, owner, u, params: StepParams, ws, stream=None) -> dict:
     """One step whose new level takes its Dirichlet data from ub's ghost layer."""
     res = Result()
-    _check(lib().subsurf4d_step_dirichlet(ctypes.byref(grid(n, h)), _p(G), _p(ub), _p(centres), int(n_centres),
-                                          _p(owner), _p(u), ctypes.byref(params.c()), ctypes.byref(res), _p(ws),
-                                          ws.numel(), _stream(stream)))
+    pG, pc, po, pu = _step_ptrs(n, G, centres, n_centres, owner, u)
+    pub = _p(ub, "u_dirichlet", "float64", 8 * _cells(n)[1])
+    _check(lib().subsurf4d_step_dirichlet(ctypes.byref(grid(n, h)), pG, pub, pc, int(n_centres), po, pu,
+                                          ctypes.byref(params.c()), ctypes.byref(res), _p(ws, "workspace"),
+                                          _nb(ws), _stream(stream)))
     return res.as_dict()
 
 
 def solve(n, h, coef, b, u, params: StepParams, ws, stream=None) -> dict:
     res = Result()
-    _check(lib().subsurf4d_solve(ctypes.byref(grid(n, h)), _p(coef), _p(b), _p(u), ctypes.byref(params.c()),
-                                 ctypes.byref(res), _p(ws), ws.numel(), _stream(stream)))
+    ni, npd = _cells(n)
+    _check(lib().subsurf4d_solve(ctypes.byref(grid(n, h)), _p(coef, "coef", "float64", 64 * ni),
+                                 _p(b, "b", "float64", 8 * ni), _p(u, "u", "float64", 8 * npd),
+                                 ctypes.byref(params.c()), ctypes.byref(res), _p(ws, "workspace"), _nb(ws),
+                                 _stream(stream)))
     return res.as_dict()
 
 
@@ -294,9 +338,9 @@ def timing(op: int = 3) -> dict:
 def copy_probe(src, dst, reps=10, stream=None) -> float:
     """Mean ms of one 16-byte-access copy of src into dst (same byte size)."""
     ms = ctypes.c_double(0.0)
-    nbytes = src.numel() * src.element_size()
-    assert dst.numel() * dst.element_size() >= nbytes
-    _check(lib().subsurf4d_copy_probe(_p(src), _p(dst), nbytes, int(reps), ctypes.byref(ms), _stream(stream)))
+    nbytes = _nb(src)
+    _check(lib().subsurf4d_copy_probe(_p(src, "src"), _p(dst, "dst", None, nbytes), nbytes, int(reps),
+                                      ctypes.byref(ms), _stream(stream)))
     return ms.value
 
 
@@ -317,11 +361,11 @@ def step_batched(jobs, params: StepParams, table, stream=None):
     Returns (status, list of per-job result dicts)."""
     arr = (BatchJobC * len(jobs))()
     for q, j in enumerate(jobs):
-        arr[q] = BatchJobC(grid(j.n, j.h), _p(j.G), _p(j.u), _p(j.owner), _p(j.centres), int(j.nc), 0,
-                           _p(j.bws), j.bws.numel())
+        pG, pc, po, pu = _step_ptrs(j.n, j.G, j.centres, j.nc, j.owner, j.u)
+        arr[q] = BatchJobC(grid(j.n, j.h), pG, pu, po, pc, int(j.nc), 0, _p(j.bws, "batch workspace"), _nb(j.bws))
     res = (Result * len(jobs))()
-    rc = _check(lib().subsurf4d_step_batched(arr, len(jobs), ctypes.byref(params.c()), res, _p(table),
-                                              0 if table is None else table.numel(), _stream(stream)))
+    rc = _check(lib().subsurf4d_step_batched(arr, len(jobs), ctypes.byref(params.c()), res,
+                                              _p(table, "table"), _nb(table), _stream(stream)))
     return rc, [r.as_dict() for r in res]
 
 
@@ -333,12 +377,15 @@ def prepare_batched(jobs, pp: PrepareParams, v, R, ball_r, table, stream=None):
     arr = (BatchPrepareJobC * len(jobs))()
     for q, j in enumerate(jobs):
         dt = {torch.uint8: U8, torch.float32: F32, torch.float64: F64}[j.image.dtype]
-        arr[q] = BatchPrepareJobC(grid(j.n, j.h), _p(j.image), dt, int(j.nc), _p(j.centres), int(j.ns), 0,
-                                  _p(j.seeds), _p(j.G), _p(j.owner), _p(j.u), _p(j.bws), j.bws.numel())
+        ni, _ = _cells(j.n)
+        pG, pc, po, pu = _step_ptrs(j.n, j.G, j.centres, j.nc, j.owner, j.u)
+        arr[q] = BatchPrepareJobC(grid(j.n, j.h), _p(j.image, "image", None, ni * j.image.element_size()), dt,
+                                  int(j.nc), pc, int(j.ns), 0, _p(j.seeds, "seeds", None, 16 * int(j.ns)),
+                                  pG, po, pu, _p(j.bws, "batch workspace"), _nb(j.bws))
     st = (ctypes.c_int32 * len(jobs))()
     rc = _check(lib().subsurf4d_prepare_batched(arr, len(jobs), ctypes.byref(pp.c()), float(v), float(R),
-                                                 float(ball_r), st, _p(table),
-                                                 0 if table is None else table.numel(), _stream(stream)))
+                                                 float(ball_r), st, _p(table, "table"), _nb(table),
+                                                 _stream(stream)))
     return rc, list(st)
 
 

@@ -213,9 +213,12 @@ int check_prepare_params(const subsurf4d_prepare_params* params)
     if (!params) return fail(SUBSURF4D_EINVAL, "NULL argument");
     const subsurf4d_prepare_params& p = *params;
     if (!(p.K >= 0.0) || !std::isfinite(p.K)) return fail(SUBSURF4D_EINVAL, "K must be >= 0");
+    if (!(p.delta >= 0.0) || !std::isfinite(p.delta) || !(p.vartheta >= 0.0) || !std::isfinite(p.vartheta))
+        return fail(SUBSURF4D_EINVAL, "delta and vartheta must be finite and >= 0");
     if (!(p.lambda >= 0.0 && p.lambda <= 1.0)) return fail(SUBSURF4D_EINVAL, "lambda must be in [0,1]");
     if (!(p.ball_r >= 0.0 && p.ball_r <= 1e6)) return fail(SUBSURF4D_EINVAL, "ball_r out of range");
-    if (!(p.smooth_tau >= 0.0) || p.smooth_steps < 0) return fail(SUBSURF4D_EINVAL, "bad smoothing parameters");
+    if (!(p.smooth_tau >= 0.0) || !std::isfinite(p.smooth_tau) || p.smooth_steps < 0)
+        return fail(SUBSURF4D_EINVAL, "bad smoothing parameters");
     if (p.smooth_steps > 0 && (!(p.smooth_omega < 2.0) || p.smooth_max_iter < 1 ||
                                !(p.smooth_tol >= 0.0)))
         return fail(SUBSURF4D_EINVAL, "bad smoothing solver parameters");

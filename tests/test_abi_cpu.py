@@ -3,6 +3,7 @@ declared in include/subsurf4d.h, and answers the host-only queries."""
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -85,3 +86,48 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
         B.workspace_bytes((8, 8, 8, 2))
     with pytest.raises(RuntimeError, match="missing"):
         B.version()
+
+
+def test_binding_rejects_host_wrong_dtype_and_short_tensors():
+    """The library sees bare addresses, so the binding checks every device
+    argument first: a host tensor, a wrong dtype or a short buffer raises
+    ValueError before any call reaches the library."""
+    import torch
+
+    from paper_2111_11866_amd import binding as B
+
+    class Dev:
+        """Stand-in for a CUDA tensor (no GPU here); its address is never taken."""
+        is_cuda = True
+
+        def __init__(self, dtype, numel, esize):
+            self.dtype, self._n, self._e = dtype, numel, esize
+
+        def is_contiguous(self):
+            return True
+
+        def numel(self):
+            return self._n
+
+        def element_size(self):
+            return self._e
+
+        def data_ptr(self):
+            raise AssertionError("address taken after a failed check")
+
+    n = (4, 3, 3, 2)
+    G = torch.zeros((4,) + B.padded_shape(n), dtype=torch.float64)
+    u = torch.zeros(B.padded_shape(n), dtype=torch.float64)
+    with pytest.raises(ValueError, match="CUDA"):
+        B.step(n, 1.0, G, None, 0, None, u, B.StepParams(rescale=False), None)
+    with pytest.raises(ValueError, match="float64"):
+        B._p(Dev("torch.float32", 10, 4), "u", "float64")
+    with pytest.raises(ValueError, match="bytes"):
+        B._p(Dev("torch.float64", 10, 8), "u", "float64", 81)
+    npad = int(np.prod([v + 2 for v in n]))
+    short_u = Dev("torch.float64", npad - 1, 8)
+    with pytest.raises(ValueError, match="u:"):
+        B.init_u(n, 1.0, None, 0, 1.0, 0.0, short_u)
+    with pytest.raises(ValueError, match="G:"):
+        B.step(n, 1.0, Dev("torch.float64", 4 * npad - 1, 8), None, 0, None, Dev("torch.float64", npad, 8),
+               B.StepParams(rescale=False), None)
