@@ -181,40 +181,66 @@ __global__ __launch_bounds__(kBlock) void kb_assemble_decide(BTable T)
     }
 }
 
-// FP64 residual of x (both colours) for unfinished jobs; r/D to FP32.
+// FP64 residual r = b - A x of the refinement, frame-marching: a work item is
+// 256 consecutive slots qf of one frame's flat numbering, and each thread
+// walks the frames l = 1..N4 of its slot for both colours, so the other
+// colour's t-neighbours and one x-neighbour stay in registers.  Writes r/D
+// (FP32, the rhs of the correction sweeps) and one partial sum of r^2 per
+// wave and item; the partials of a job do not depend on the rest of the
+// batch.
 __global__ __launch_bounds__(kBlock) void kb_residual(BTable T)
 {
-    for_runs(T.act_both, T.act_jobs, *T.n_act, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
+    for_runs(T.act_colf, T.act_jobs, *T.n_act, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
         const BJob J = T.jobs[jb];
         const uint32_t sy = J.rsu, sz = (uint32_t)J.p2 * J.rsu, st = sz * (uint32_t)J.p3;
-        const uint32_t nit = (uint32_t)J.nit;
-        SS4_GLOBAL const double* xr = gbl(static_cast<const double*>(J.xr));
-        SS4_GLOBAL const double* xb = gbl(static_cast<const double*>(J.xb));
+        const uint32_t nqf = (uint32_t)J.nqf;
         SS4_GLOBAL const double* coef = gbl(static_cast<const double*>(J.coef));
         SS4_GLOBAL float* rf = gbl(J.rf);
         SS4_GLOBAL double* pa = gbl(J.part_a);
         for (uint32_t item = i0; item < i1; item += step) {
-            const int colour = item >= nit ? 1 : 0;
-            const uint32_t q = (item - (colour ? nit : 0u)) * kItem + threadIdx.x;
+            const uint32_t qf = item * kItem + threadIdx.x;
             double acc = 0.0;
-            Cell c;
-            if (bdecode(J, colour, q, c)) {
-                const uint32_t ui = c.prow * J.rsu + 1 + c.m;
-                SS4_GLOBAL const double* own = colour ? xb : xr;
-                SS4_GLOBAL const double* oth = colour ? xr : xb;
-                SS4_GLOBAL const double* cf = coef + bctile(J, colour, q);
-                const double c0 = cf[0], c1 = cf[kTileSlots], c2 = cf[2 * kTileSlots], c3 = cf[3 * kTileSlots];
-                const double c4 = cf[4 * kTileSlots], c5 = cf[5 * kTileSlots], c6 = cf[6 * kTileSlots];
-                const double c7 = cf[7 * kTileSlots];
-                double s = cf[8 * kTileSlots];
-                s += c0 * oth[ui - c.par] + c1 * oth[ui + 1 - c.par];
-                s += c2 * oth[ui - sy] + c3 * oth[ui + sy];
-                s += c4 * oth[ui - sz] + c5 * oth[ui + sz];
-                s += c6 * oth[ui - st] + c7 * oth[ui + st];
-                const double D = ((((((((1.0 + c0) + c1) + c2) + c3) + c4) + c5) + c6) + c7);
-                const double res = s - D * own[ui];
-                acc = res * res;
-                rf[(uint32_t)colour * (uint32_t)J.ntq * kTileSlots + q] = (float)(res / D);
+            if (qf < nqf) {
+                const uint32_t r = fdiv(qf, J.mg_half);
+                const int m = (int)(qf - r * (uint32_t)J.half);
+                const uint32_t r2 = fdiv(r, J.mg_n2);
+                const int j = (int)(r - r2 * (uint32_t)J.n2) + 1;
+                const int k = (int)r2 + 1;
+                const uint32_t u0 = ((uint32_t)k * J.p2 + (uint32_t)j) * J.rsu + 1 + m;   // row (j,k,l=0)
+#pragma unroll
+                for (int colour = 0; colour < 2; ++colour) {
+                    SS4_GLOBAL const double* own = gbl(static_cast<const double*>(colour ? J.xb : J.xr));
+                    SS4_GLOBAL const double* oth = gbl(static_cast<const double*>(colour ? J.xr : J.xb));
+                    const uint32_t cb = (uint32_t)colour * (uint32_t)J.ntq * kTileSlots;
+                    double Bm = oth[u0];
+                    double Bc = oth[u0 + st];
+                    for (int l = 1; l <= J.n4; ++l) {
+                        const uint32_t ui = u0 + (uint32_t)l * st;
+                        const double Bp = oth[ui + st];
+                        const int par = (colour + j + k + l) & 1;
+                        const int cnt = par ? (J.n1 + 1) >> 1 : J.n1 >> 1;
+                        if (m < cnt) {
+                            const uint32_t q = (uint32_t)(l - 1) * nqf + qf;
+                            SS4_GLOBAL const double* cf = coef + bctile(J, colour, q);
+                            const double c0 = cf[0], c1 = cf[kTileSlots], c2 = cf[2 * kTileSlots];
+                            const double c3 = cf[3 * kTileSlots], c4 = cf[4 * kTileSlots];
+                            const double c5 = cf[5 * kTileSlots], c6 = cf[6 * kTileSlots];
+                            const double c7 = cf[7 * kTileSlots];
+                            const double xo = oth[par ? ui - 1 : ui + 1];
+                            double s = cf[8 * kTileSlots];
+                            s += c0 * (par ? xo : Bc) + c1 * (par ? Bc : xo);
+                            s += c2 * oth[ui - sy] + c3 * oth[ui + sy];
+                            s += c4 * oth[ui - sz] + c5 * oth[ui + sz];
+                            s += c6 * Bm + c7 * Bp;
+                            const double D = ((((((((1.0 + c0) + c1) + c2) + c3) + c4) + c5) + c6) + c7);
+                            const double res = s - D * own[ui];
+                            acc += res * res;
+                            rf[cb + q] = (float)(res / D);
+                        }
+                        Bm = Bc;
+                        Bc = Bp;
+                    }
+                }
             }
             const double ws = wave_sum(acc);
             if ((threadIdx.x & 63) == 0) pa[item * kWaves + (threadIdx.x >> 6)] = ws;
@@ -231,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void kb_residual_decide(BTable T)
     const int na = *T.n_act;
     for (int a = blockIdx.x; a < na; a += gridDim.x) {
         const BJob& J = T.jobs[T.act_jobs[a]];
-        const double R2 = sum_partials(J.part_a, (int)(kWaves * 2 * J.nit), lds);
+        const double R2 = sum_partials(J.part_a, (int)(kWaves * J.nitf), lds);
         if (threadIdx.x == 0) {
             Ctrl* C = J.C;
             const double R = sqrt(R2);
