@@ -208,7 +208,8 @@ def _nb(t):
 
 def _cells(n):
     """(interior, padded) cell counts of grid n."""
-    return int(np.prod(n)), int(np.prod([v + 2 for v in n]))
+    n1, n2, n3, n4 = (int(v) for v in n)
+    return n1 * n2 * n3 * n4, (n1 + 2) * (n2 + 2) * (n3 + 2) * (n4 + 2)
 
 
 def _stream(stream=None):
@@ -356,13 +357,31 @@ def batch_table_bytes(n_jobs) -> int:
     return int(lib().subsurf4d_batch_table_bytes(int(n_jobs)))
 
 
+def _batch_job_c(j):
+    """The checked descriptor of a batched job.  It is kept on the job object
+    and reused while the job's tensors keep their addresses and sizes and its
+    shape is unchanged, so a step of many windows does not re-check every
+    tensor of every window."""
+    key = (tuple(None if t is None else (t.data_ptr(), t.numel()) for t in (j.G, j.u, j.owner, j.centres, j.bws)),
+           tuple(j.n), float(j.h), int(j.nc))
+    cached = getattr(j, "_ss4_batch_c", None)
+    if cached is not None and cached[0] == key:
+        return cached[1]
+    pG, pc, po, pu = _step_ptrs(j.n, j.G, j.centres, j.nc, j.owner, j.u)
+    c = BatchJobC(grid(j.n, j.h), pG, pu, po, pc, int(j.nc), 0, _p(j.bws, "batch workspace"), _nb(j.bws))
+    try:
+        j._ss4_batch_c = (key, c)
+    except AttributeError:
+        pass
+    return c
+
+
 def step_batched(jobs, params: StepParams, table, stream=None):
     """jobs: sequence of objects with n, h, G, u, owner, centres, nc, bws (batch workspace).
     Returns (status, list of per-job result dicts)."""
     arr = (BatchJobC * len(jobs))()
     for q, j in enumerate(jobs):
-        pG, pc, po, pu = _step_ptrs(j.n, j.G, j.centres, j.nc, j.owner, j.u)
-        arr[q] = BatchJobC(grid(j.n, j.h), pG, pu, po, pc, int(j.nc), 0, _p(j.bws, "batch workspace"), _nb(j.bws))
+        arr[q] = _batch_job_c(j)
     res = (Result * len(jobs))()
     rc = _check(lib().subsurf4d_step_batched(arr, len(jobs), ctypes.byref(params.c()), res,
                                               _p(table, "table"), _nb(table), _stream(stream)))
