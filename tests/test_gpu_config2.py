@@ -237,3 +237,34 @@ def test_converged_step_residual_rows(c2):
         D = 1.0 + float(np.sum(c))
         res = b + float(np.dot(c, nb)) - D * un[1, 1, 1, 1]
         assert abs(res) <= bound, (p, res, bound)
+
+
+def test_mixed_step_full_size(c2):
+    """The mixed-precision step on the whole volume (FP32 sweeps on BF16
+    coefficients, FP64 refinement to ||r||_2 <= 1e-10 ||b||_2) against the
+    FP64 step converged to 1e-12 from the same level.  With ||A^-1||_inf <= 1
+    (stability section) every cell's error is at most ||r||_inf <= ||r||_2, so
+    both results lie within their tolerance times ||b||_2 of the exact
+    solution, and of each other within the sum."""
+    from dataclasses import replace
+
+    job, sp = c2["job"], replace(c2["sp"], rescale=False)
+    w0 = c2["w0"]
+    ref = w0.clone()
+    r64 = B.step(N, 1.0, job.G, job.centres, job.nc, job.owner, ref, replace(sp, tol=1e-12, max_iter=100000),
+                 job.ws)
+    assert r64["status"] == 0
+    ws = B.alloc_workspace(N, job.nc, B.MIXED)
+    u = w0.clone()
+    mixed = replace(sp, precision=B.MIXED, refine_tol=1e-10, inner_sweeps=10, omega=1.5)
+    r = B.step(N, 1.0, job.G, job.centres, job.nc, job.owner, u, mixed, ws)
+    del ws
+    assert r["status"] == 0 and r["rel_res"] <= 1e-10
+    bnorm = r64["bnorm"]
+    assert abs(r["bnorm"] - bnorm) <= 1e-12 * bnorm
+    err = float((u - ref).abs().max())
+    assert err <= (1e-10 + 1e-12) * bnorm * (1.0 + 1e-6), (err, bnorm)
+    rel_l2 = float(torch.linalg.vector_norm(u - ref) / torch.linalg.vector_norm(ref))
+    print(f"mixed vs converged FP64 on the full volume: max-abs {err:.3e} (bound "
+          f"{1.01e-10 * bnorm:.3e}), relative L2 {rel_l2:.3e}, {r['outer']} passes")
+    del u, ref
