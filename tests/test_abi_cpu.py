@@ -131,3 +131,48 @@ def test_binding_rejects_host_wrong_dtype_and_short_tensors():
     with pytest.raises(ValueError, match="G:"):
         B.step(n, 1.0, Dev("torch.float64", 4 * npad - 1, 8), None, 0, None, Dev("torch.float64", npad, 8),
                B.StepParams(rescale=False), None)
+
+
+def test_header_compiles_as_c_and_links(tmp_path):
+    """include/subsurf4d.h is plain C: a C99 program including it builds with
+    gcc -std=c99 -pedantic -Wall -Werror, links libsubsurf4d.so and answers
+    the host-only queries (no GPU is touched)."""
+    import shutil
+    import subprocess
+
+    from paper_2111_11866_amd import binding as B
+
+    gcc = shutil.which("gcc")
+    if gcc is None or not os.path.exists(B.LIB_PATH):
+        pytest.skip("gcc or the built library is missing")
+    src = tmp_path / "use_abi.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <string.h>
+#include "subsurf4d.h"
+
+int main(void)
+{
+    subsurf4d_grid g;
+    size_t ws, wm, wb, tb;
+    g.n[0] = 40; g.n[1] = 30; g.n[2] = 20; g.n[3] = 5; g.h = 1.0;
+    ws = subsurf4d_workspace_bytes(&g, 3, SUBSURF4D_FP64);
+    wm = subsurf4d_workspace_bytes(&g, 3, SUBSURF4D_MIXED);
+    wb = subsurf4d_batch_workspace_bytes(&g, 3);
+    tb = subsurf4d_batch_table_bytes(16);
+    if (ws == 0 || wm <= ws || wb == 0 || tb == 0) return 2;
+    g.n[0] = 0;
+    if (subsurf4d_workspace_bytes(&g, 0, SUBSURF4D_FP64) != 0) return 3;
+    if (strlen(subsurf4d_status_string(SUBSURF4D_EWORKSPACE)) == 0) return 4;
+    printf("%zu %zu %zu %zu %s\n", ws, wm, wb, tb, subsurf4d_version());
+    return 0;
+}
+''')
+    exe = tmp_path / "use_abi"
+    libdir = os.path.dirname(B.LIB_PATH)
+    subprocess.run([gcc, "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-L", libdir, "-lsubsurf4d", "-Wl,-rpath," + libdir, "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert out.returncode == 0, (out.returncode, out.stderr)
+    ws = int(out.stdout.split()[0])
+    assert ws == B.workspace_bytes((40, 30, 20, 5), 3, B.FP64)
