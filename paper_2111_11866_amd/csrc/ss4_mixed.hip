@@ -50,41 +50,54 @@ __global__ __launch_bounds__(kBlock) void k_mx_residual(MxArgs a)
     const Layout& L = a.L;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int ntm = (L.half + 63) >> 6;
-    const int64_t rows = 2 * L.nrow_int;
-    const int64_t ntr = (rows + 3) >> 2;
+    const int njb = (L.n2 + 3) >> 2;
+    const int64_t ncol = (int64_t)ntm * njb * L.n3;
     const int64_t sy = L.rs, sz = (int64_t)L.p2 * L.rs, st = (int64_t)L.p2 * L.p3 * L.rs;
     double acc = 0.0;
-    for (TileWalk tw(ntm * ntr); tw.t < tw.end; tw.t += tw.step) {
-        const int64_t tr = tw.t / ntm;
-        const int tm = (int)(tw.t - tr * ntm);
-        const int64_t rr = tr * 4 + ty;
-        if (rr >= rows) continue;
-        const int colour = rr >= L.nrow_int ? 1 : 0;
-        const int64_t r = rr - colour * L.nrow_int;
-        const int m = tm * 64 + tx;
-        const int j = (int)(r % L.n2) + 1;
-        const int64_t r2 = r / L.n2;
-        const int k = (int)(r2 % L.n3) + 1;
-        const int l = (int)(r2 / L.n3) + 1;
-        const int par = (colour + j + k + l) & 1;
-        const int cnt = par ? (L.n1 + 1) >> 1 : L.n1 >> 1;
-        if (m >= cnt) continue;
-        const int64_t ui = (((int64_t)l * L.p3 + k) * L.p2 + j) * L.rs + L.xoff + m;
-        const double* own = colour ? a.xb : a.xr;
-        const double* oth = colour ? a.xr : a.xb;
-        const double* cf = a.coef + ctile(L, colour, r, m);
-        const double c0 = cf[0], c1 = cf[kTileSlots], c2 = cf[2 * kTileSlots], c3 = cf[3 * kTileSlots];
-        const double c4 = cf[4 * kTileSlots], c5 = cf[5 * kTileSlots], c6 = cf[6 * kTileSlots];
-        const double c7 = cf[7 * kTileSlots];
-        double s = cf[8 * kTileSlots];
-        s += c0 * oth[ui - par] + c1 * oth[ui + 1 - par];
-        s += c2 * oth[ui - sy] + c3 * oth[ui + sy];
-        s += c4 * oth[ui - sz] + c5 * oth[ui + sz];
-        s += c6 * oth[ui - st] + c7 * oth[ui + st];
-        const double D = ((((((((1.0 + c0) + c1) + c2) + c3) + c4) + c5) + c6) + c7);
-        const double res = s - D * own[ui];
-        acc += res * res;
-        a.rf[mrec(L, colour, r, m)] = (float)(res / D);
+    // a block owns a 64-slot x 4-row column tile at one z and walks the
+    // frames for both colours; the other colour's t-neighbours stay in
+    // registers (tiles dealt slot-tile fastest, then z, as the sweeps)
+    for (TileWalk tw(ncol); tw.t < tw.end; tw.t += tw.step) {
+        const int mt = (int)(tw.t % ntm);
+        const int64_t t2 = tw.t / ntm;
+        const int k = (int)(t2 % L.n3) + 1;
+        const int jb = (int)(t2 / L.n3);
+        const int j = jb * 4 + ty + 1;
+        const int m = mt * 64 + tx;
+        if (j > L.n2 || m >= L.half) continue;
+        const int64_t ub = ((int64_t)k * L.p2 + j) * L.rs + L.xoff + m;
+        const int64_t rb = (int64_t)(k - 1) * L.n2 + (j - 1);
+        for (int colour = 0; colour < 2; ++colour) {
+            const double* own = colour ? a.xb : a.xr;
+            const double* oth = colour ? a.xr : a.xb;
+            double Bm = oth[ub];
+            double Bc = oth[ub + st];
+            for (int l = 1; l <= L.n4; ++l) {
+                const int64_t ui = ub + (int64_t)l * st;
+                const double Bp = oth[ui + st];
+                const int par = (colour + j + k + l) & 1;
+                const int cnt = par ? (L.n1 + 1) >> 1 : L.n1 >> 1;
+                if (m < cnt) {
+                    const int64_t r = rb + (int64_t)(l - 1) * L.n3 * L.n2;
+                    const double* cf = a.coef + ctile(L, colour, r, m);
+                    const double c0 = cf[0], c1 = cf[kTileSlots], c2 = cf[2 * kTileSlots], c3 = cf[3 * kTileSlots];
+                    const double c4 = cf[4 * kTileSlots], c5 = cf[5 * kTileSlots], c6 = cf[6 * kTileSlots];
+                    const double c7 = cf[7 * kTileSlots];
+                    const double xo = oth[par ? ui - 1 : ui + 1];
+                    double s = cf[8 * kTileSlots];
+                    s += c0 * (par ? xo : Bc) + c1 * (par ? Bc : xo);
+                    s += c2 * oth[ui - sy] + c3 * oth[ui + sy];
+                    s += c4 * oth[ui - sz] + c5 * oth[ui + sz];
+                    s += c6 * Bm + c7 * Bp;
+                    const double D = ((((((((1.0 + c0) + c1) + c2) + c3) + c4) + c5) + c6) + c7);
+                    const double res = s - D * own[ui];
+                    acc += res * res;
+                    a.rf[mrec(L, colour, r, m)] = (float)(res / D);
+                }
+                Bm = Bc;
+                Bc = Bp;
+            }
+        }
     }
     const double bs = block_sum(acc, lds);
     if (threadIdx.x == 0) a.part[blockIdx.x] = bs;
@@ -252,6 +265,7 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
 
     const int64_t row_tiles = (int64_t)((L.half + 63) >> 6) * ((2 * L.nrow_int + 3) >> 2);
     const int grid_rows = grid_for(row_tiles, 1);
+    const int grid_res = resident_grid(reinterpret_cast<const void*>(&k_mx_residual));
     const int64_t ncol = (int64_t)((L.half + 63) >> 6) * ((L.n2 + 3) >> 2) * L.n3;
     // one cell per lane: two cells per lane (as the FP64 sweep) measured slower
     // for the FP32 correction (3.36 vs 4.13 TB/s on the 512x512x96x16 volume)
@@ -265,7 +279,7 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
     int pass = 0;
     while (!hc.done) {
         a.pass = pass;
-        k_mx_residual<<<grid_rows, kBlock, 0, s>>>(a);
+        k_mx_residual<<<grid_res, kBlock, 0, s>>>(a);
         SS4_LAUNCHED("mixed: residual");
         SS4_HIP(hipMemcpyAsync(&hc, C, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
         SS4_HIP(hipStreamSynchronize(s));
