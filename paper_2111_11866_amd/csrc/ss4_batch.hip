@@ -22,6 +22,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "ss4_batch.hpp"
@@ -716,7 +717,7 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
     SS4_LAUNCHED("batched: assemble");
 
     // Autotuner of the inner sweep's 4D tile shape and launch shape: the first
-    // batch with a given signature times both work shapes (flat 256-cell items,
+    // batch with a given signature (device, job count, items) times both work shapes (flat 256-cell items,
     // or 256-slot x N4-frame marching columns) at grids of 1, 2 and 4 times
     // the resident size on its own data and keeps the fastest.  Shape and grid
     // change only which thread updates which cell, never a job's arithmetic
@@ -749,8 +750,10 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
                           : resident_grid(reinterpret_cast<const void*>(&kb_sweep_tm<0, false>));
     } else {
         static std::mutex mu;
-        static std::map<std::pair<int, int64_t>, std::pair<int, int>> tuned;
-        const auto key = std::make_pair(n_jobs, col_start[n_jobs]);
+        static std::map<std::tuple<int, int, int64_t>, std::pair<int, int>> tuned;
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        const auto key = std::make_tuple(dev, n_jobs, col_start[n_jobs]);
         {
             std::lock_guard<std::mutex> g(mu);
             auto it = tuned.find(key);

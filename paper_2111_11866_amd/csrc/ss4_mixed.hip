@@ -268,7 +268,9 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
     const int grid_res = resident_grid(reinterpret_cast<const void*>(&k_mx_residual));
     const int64_t ncol = (int64_t)((L.half + 63) >> 6) * ((L.n2 + 3) >> 2) * L.n3;
     // one cell per lane: two cells per lane (as the FP64 sweep) measured slower
-    // for the FP32 correction (3.36 vs 4.13 TB/s on the 512x512x96x16 volume)
+    // for the FP32 correction, in two designs (3.36 vs 4.13 TB/s on the
+    // 512x512x96x16 volume; a tile-per-wave form with contiguous 2 KB record
+    // runs and 8-byte d accesses, same bits: 165.7 vs 162.1 ms per step)
     const int res_g = resident_grid(reinterpret_cast<const void*>(&k_mx_sweep<0, false>)) / 2;
     const int grid_cols = (int)(((ncol < res_g ? ncol : res_g) + kXcd - 1) / kXcd * kXcd);
 
