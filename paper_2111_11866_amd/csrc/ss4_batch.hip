@@ -417,10 +417,11 @@ __global__ __launch_bounds__(kScan) void kb_compact(BTable T)
     s_sum[threadIdx.x] = sum;
     s_sumf[threadIdx.x] = sumf;
     __syncthreads();
+    const int tid = (int)threadIdx.x;
     for (int d = 1; d < kScan; d <<= 1) {            // inclusive Hillis-Steele scan
-        const int c = threadIdx.x >= d ? s_cnt[threadIdx.x - d] : 0;
-        const int64_t v = threadIdx.x >= d ? s_sum[threadIdx.x - d] : 0;
-        const int64_t vf = threadIdx.x >= d ? s_sumf[threadIdx.x - d] : 0;
+        const int c = tid >= d ? s_cnt[tid - d] : 0;
+        const int64_t v = tid >= d ? s_sum[tid - d] : 0;
+        const int64_t vf = tid >= d ? s_sumf[tid - d] : 0;
         __syncthreads();
         s_cnt[threadIdx.x] += c;
         s_sum[threadIdx.x] += v;
