@@ -613,6 +613,10 @@ int bind_batch_job(const int32_t n[4], int32_t nc, void* ws, size_t ws_bytes, BJ
 // called on it runs on a library-owned non-blocking stream (default priority,
 // one per device), ordered after the caller's earlier work by an event; the
 // call synchronises before it returns.
+// batches with fewer work items per colour than this skip the sweep-shape
+// tuning run (about 26 windows of 40^3 x 5 cells)
+constexpr int64_t kTuneMinItems = 1 << 14;
+
 hipStream_t side_stream()
 {
     static std::mutex mu;
@@ -751,11 +755,27 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
                           : resident_grid(reinterpret_cast<const void*>(&kb_sweep_tm<0, false>));
     } else {
         static std::mutex mu;
-        static std::map<std::tuple<int, int, int64_t>, std::pair<int, int>> tuned;
+        // the signature is coarse on purpose: batches whose job sets differ but
+        // whose total work (half-octave buckets of the item count) and
+        // cell-weighted mean frame count agree share one decision, so a
+        // serving loop whose batch changes every step does not re-tune it;
+        // small batches (where a tuning run would cost more than it can save)
+        // take the frame-marching shape at the resident grid untimed
+        static std::map<std::tuple<int, int, int>, std::pair<int, int>> tuned;
         int dev = 0;
         (void)hipGetDevice(&dev);
-        const auto key = std::make_tuple(dev, n_jobs, col_start[n_jobs]);
-        {
+        double cells = 0.0, frames = 0.0;
+        for (int q = 0; q < n_jobs; ++q) {
+            cells += (double)hj[q].nint;
+            frames += (double)hj[q].nint * hj[q].n4;
+        }
+        const int work_bucket = (int)std::floor(2.0 * std::log2((double)col_start[n_jobs] + 1.0));
+        const int mean_frames = (int)std::lround(cells > 0.0 ? frames / cells : 1.0);
+        const auto key = std::make_tuple(dev, work_bucket, mean_frames);
+        if (col_start[n_jobs] < kTuneMinItems) {
+            shape = 1;
+            g_sw = resident_grid(reinterpret_cast<const void*>(&kb_sweep_tm<0, false>));
+        } else {
             std::lock_guard<std::mutex> g(mu);
             auto it = tuned.find(key);
             if (it != tuned.end()) { shape = it->second.first; g_sw = it->second.second; }
