@@ -367,8 +367,8 @@ def test_eoc_second_order(orc):
     assert np.log2(e10 / e20) >= 1.8
 
 
-@pytest.mark.slow
 def test_eoc_n40(orc):
+    """The same at n=40 (16 steps; about 20 s on 8 host cores)."""
     rows = _table()
     e20, _ = orc.eoc_run(20, 4)
     e40, _ = orc.eoc_run(40, 16)
