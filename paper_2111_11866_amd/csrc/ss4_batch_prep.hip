@@ -28,6 +28,7 @@ struct PTable {
     BJob* jobs;
     int4* out;            // per job: status / iterations of the I0 and I^TH heat solves
     int64_t* int_start;   // prefix of interior work items
+    int64_t* col_start;   // prefix of one colour's work items (flat per-colour numbering)
     int64_t* pad_start;   // prefix of padded work items
     int64_t* ball_start;  // prefix of centres
     int64_t* seed_start;  // prefix of seeds
@@ -341,17 +342,20 @@ __global__ __launch_bounds__(kBlock) void kp_lhe_decide(PTable T)
 template <int COLOR>
 __global__ __launch_bounds__(kBlock) void kp_lhe_sweep(PTable T)
 {
+    // one lane per cell of colour COLOR: a work item is 256 consecutive q of
+    // the colour's flat numbering q = r*half + m (cell i = 2m + 2 - par of
+    // interior row r), so no lane idles on the other colour
     const double a = T.a, om = T.omega, om1 = 1.0 - T.omega;
-    for_runs(T.int_start, nullptr, T.n_jobs, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
+    for_runs(T.col_start, nullptr, T.n_jobs, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
         const BJob J = T.jobs[jb];
         const bool run0 = !J.C->done, run1 = !J.C2->done;
         if (!run0 && !run1) return;
-        const uint32_t n = (uint32_t)J.nint;
         for (uint32_t item = i0; item < i1; item += step) {
-            const uint32_t q = item * kItem + threadIdx.x;
-            if (q >= n) continue;
-            const ICell c = idecode(J, q);
-            if (((c.i + c.j + c.k + c.l) & 1) != COLOR) continue;
+            Cell cc;
+            if (!bdecode(J, COLOR, item * kItem + threadIdx.x, cc)) continue;
+            const ICell c{2 * cc.m + 2 - cc.par, cc.j, cc.k, cc.l};
+            const uint32_t q = ((((uint32_t)c.l - 1) * (uint32_t)J.n3 + ((uint32_t)c.k - 1)) * (uint32_t)J.n2 +
+                                ((uint32_t)c.j - 1)) * (uint32_t)J.n1 + ((uint32_t)c.i - 1);
             double D;
             if (run0) {
                 const double s = lhe_row(J, a, J.I0, J.S0, q, c, &D);
@@ -522,7 +526,8 @@ int run_batch_prepare_on(const subsurf4d_batch_prepare_job* jobs, int n_jobs, co
                          hipStream_t s)
 {
     std::vector<BJob> hj(n_jobs);
-    std::vector<int64_t> int_start(n_jobs + 1, 0), pad_start(n_jobs + 1, 0), ball_start(n_jobs + 1, 0),
+    std::vector<int64_t> int_start(n_jobs + 1, 0), col_start(n_jobs + 1, 0), pad_start(n_jobs + 1, 0),
+        ball_start(n_jobs + 1, 0),
         seed_start(n_jobs + 1, 0);
     for (int q = 0; q < n_jobs; ++q) {
         const subsurf4d_batch_prepare_job& pj = jobs[q];
@@ -549,6 +554,7 @@ int run_batch_prepare_on(const subsurf4d_batch_prepare_job* jobs, int n_jobs, co
         J.ns = pj.n_seeds;
         hj[q] = J;
         int_start[q + 1] = int_start[q] + (J.nint + kItem - 1) / kItem;
+        col_start[q + 1] = col_start[q] + J.nit;
         pad_start[q + 1] = pad_start[q] + J.nip;
         ball_start[q + 1] = ball_start[q] + J.nc;
         seed_start[q + 1] = seed_start[q] + J.ns;
@@ -563,6 +569,7 @@ int run_batch_prepare_on(const subsurf4d_batch_prepare_job* jobs, int n_jobs, co
     T.jobs = reinterpret_cast<BJob*>(tb + off); off += al256(sizeof(BJob) * n_jobs);
     T.out = reinterpret_cast<int4*>(tb + off); off += al256(sizeof(Ctrl) * n_jobs);
     T.int_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
+    T.col_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
     T.pad_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
     T.ball_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
     T.seed_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
@@ -575,6 +582,7 @@ int run_batch_prepare_on(const subsurf4d_batch_prepare_job* jobs, int n_jobs, co
     T.omega = 1.0;
     SS4_HIP(hipMemcpyAsync(T.jobs, hj.data(), sizeof(BJob) * n_jobs, hipMemcpyHostToDevice, s));
     SS4_HIP(hipMemcpyAsync(T.int_start, int_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
+    SS4_HIP(hipMemcpyAsync(T.col_start, col_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
     SS4_HIP(hipMemcpyAsync(T.pad_start, pad_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
     SS4_HIP(hipMemcpyAsync(T.ball_start, ball_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
     SS4_HIP(hipMemcpyAsync(T.seed_start, seed_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));

@@ -221,14 +221,20 @@ __global__ __launch_bounds__(kBlock) void k_lhe_sweep(Layout L, double a, double
 {
     if (C->done) return;
     const int64_t sy = L.n1, sz = (int64_t)L.n1 * L.n2, st = sz * L.n3;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < L.nint; q += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(q % L.n1) + 1;
-        const int64_t row = q / L.n1;
+    // one lane per cell of colour COLOR: h = row*half + m walks the colour's
+    // cells (cell i = 2m + 2 - par of the row), so no lane idles
+    const int64_t ncq = L.nrow_int * L.half;
+    for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < ncq; h += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = h / L.half;
+        const int m = (int)(h - row * L.half);
         const int j = (int)(row % L.n2) + 1;
         const int64_t r2 = row / L.n2;
         const int k = (int)(r2 % L.n3) + 1;
         const int l = (int)(r2 / L.n3) + 1;
-        if (((i + j + k + l) & 1) != COLOR) continue;
+        const int par = (COLOR + j + k + l) & 1;
+        if (m >= (par ? (L.n1 + 1) >> 1 : L.n1 >> 1)) continue;
+        const int i = 2 * m + 2 - par;
+        const int64_t q = row * L.n1 + (i - 1);
         double s = rhs[q];
         int cnt = 0;
         if (i > 1) { s += a * J[q - 1]; ++cnt; }
@@ -398,10 +404,10 @@ int lhe_solve(const WsPlan& P, double a, double omega, double tol, int max_iter,
     Ctrl* C = ws_ptr<Ctrl>(ws, P.ctrl);
     double* pa = ws_ptr<double>(ws, P.part_a);
     double* pb = ws_ptr<double>(ws, P.part_b);
-    const int gs = grid_for(L.nint);
+    const int gs = grid_for(L.nrow_int * L.half);
     // the residual's per-block partials fit the workspace's partial arrays
-    // (at least kGridCap entries), so it takes the sweep's grid
-    const int gr = gs;
+    // (at least kGridCap entries), so it takes a full grid as well
+    const int gr = grid_for(L.nint);
     k_copy_f64<<<grid_for(L.nint), kBlock, 0, s>>>(rhs, J, L.nint);
     k_ctrl_init<<<1, 64, 0, s>>>(C, tol, max_iter);
     k_lhe_residual<<<gr, kBlock, 0, s>>>(L, a, rhs, J, 0, pa, pb, C);
