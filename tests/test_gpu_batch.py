@@ -212,3 +212,32 @@ def test_batched_window_at_the_size_limit():
     for (j, _, _), ref in zip(made, refs):
         err = np.abs(H(j.u) - ref).max()
         assert err <= 1e-7 * np.abs(ref).max(), (j.n, err)
+
+
+def test_batched_grid_spacing_and_dirichlet_data():
+    """Jobs of different grid spacing (h = 0.37, 1, 2.5: tau/h^2 and the
+    gradients scale per job) with non-zero Dirichlet data in their ghost
+    layers, in one batch, each against the FP64 oracle converged to 1e-14."""
+    from dataclasses import replace
+
+    rng = np.random.default_rng(43)
+    made = []
+    for n, h in (((9, 7, 6, 5), 0.37), ((24, 20, 18, 3), 1.0), ((13, 11, 9, 4), 2.5)):
+        j, G, _ = raw_job(n, rng)
+        w = rng.uniform(0.0, 1.0, size=B.padded_shape(n))           # ghosts = u^D, not zero
+        j.u = torch.from_numpy(w).to("cuda")
+        j.h = h
+        made.append((j, G, w, h))
+    rc, res = run([m[0] for m in made], replace(SP, rescale=False))
+    assert rc == 0
+    for (j, G, w, h), r in zip(made, res):
+        assert r["status"] == 0, (j.n, h, r)
+        ref = orc.step(j.n, G, w, None, None, orc.StepParams(tol=1e-14, rescale=False, h=h), orc.RB)["u_resc"]
+        got = H(j.u)
+        err = np.abs(got - ref).max()
+        assert err <= 1e-8 * np.abs(ref).max(), (j.n, h, err)
+        # the ghost layer (Dirichlet data) is left as it was
+        inner = (slice(1, -1),) * 4
+        mask = np.ones(got.shape, bool)
+        mask[inner] = False
+        assert np.array_equal(got[mask], w[mask])
