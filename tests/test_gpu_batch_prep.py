@@ -143,3 +143,25 @@ def test_batched_prepare_bad_arguments(imgs):
                 dict(smooth_tau=float("inf"))):
         with pytest.raises(B.Subsurf4dError):
             B.prepare_batched(jobs, replace(PP, **bad), 1.0, 0.0, BALL_R, table)
+
+
+def test_prepare_grid_spacing_single_and_batched():
+    """h = 0.5 enters the presmoothing (tau_s / h^2) and the face gradients of
+    G (ball membership and u0 are in voxel units): the batched and the
+    single-job preparation against the oracle."""
+    h = 0.5
+    ims = windows([(26, 24, 22, 3), (30, 25, 21, 4)], seed0=7000)
+    jobs = [B.Job(im.n, im.image, im.centres, im.seeds, h=h, precision=B.MIXED, batch=True, shared_ws=False)
+            for im in ims]
+    table = torch.empty(B.batch_table_bytes(len(jobs)), dtype=torch.uint8, device="cuda")
+    rc, st = B.prepare_batched(jobs, PP, 1.0, 0.0, BALL_R, table)
+    assert rc == 0 and st == [0] * len(jobs)
+    for im, j in zip(ims, jobs):
+        I0 = im.image.astype(np.float64) * PP.image_scale
+        prep = orc.prepare(im.n, I0, im.centres, replace(orc_pp(PP), h=h))
+        np.testing.assert_array_equal(H(j.owner), prep["owner"])
+        assert np.abs(H(j.G) - prep["G"]).max() <= 1e-12
+        one = B.Job(im.n, im.image, im.centres, im.seeds, h=h, precision=B.FP64)
+        assert one.prepare(PP) == 0
+        np.testing.assert_array_equal(H(one.owner), prep["owner"])
+        assert np.abs(H(one.G) - prep["G"]).max() <= 1e-12
