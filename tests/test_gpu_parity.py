@@ -253,6 +253,22 @@ def test_solve_tolerance_same_iterations(n):
         assert np.abs(H(u)[1:-1, 1:-1, 1:-1, 1:-1] - ref[1:-1, 1:-1, 1:-1, 1:-1]).max() <= 1e-12
 
 
+@pytest.mark.parametrize("n,check", [((5, 4, 3, 3), 3), ((33, 9, 7, 3), 4), ((130, 3, 2, 2), 5)])
+def test_solve_check_every(n, check):
+    """With check_every = c the stopping rule is tested at k = 0, c, 2c, ...:
+    the GPU stops at the oracle's iteration (a multiple of c) with its iterate."""
+    G, w, coef, b = random_system(n, 7 * sum(n))
+    sp = B.StepParams(omega=1.5, tol=1e-9, rescale=False, check_every=check)
+    u = T(w)
+    r = B.solve(n, 1.0, T(coef), T(b), u, sp, B.alloc_workspace(n))
+    ref, it, rr, st = orc.sor(n, coef, b, w, 1.5, 1e-9, 10000, orc.RB, check)
+    assert it % check == 0 and r["iterations"] % check == 0
+    if r["iterations"] != it:
+        assert abs(rr / 1e-9 - 1) < 1e-6, (r, it, rr)
+    else:
+        assert np.abs(H(u)[1:-1, 1:-1, 1:-1, 1:-1] - ref[1:-1, 1:-1, 1:-1, 1:-1]).max() <= 1e-12
+
+
 # ---------------------------------------------------------------------- step
 
 
