@@ -269,6 +269,31 @@ def test_solve_check_every(n, check):
         assert np.abs(H(u)[1:-1, 1:-1, 1:-1, 1:-1] - ref[1:-1, 1:-1, 1:-1, 1:-1]).max() <= 1e-12
 
 
+@pytest.mark.parametrize("tau", [5.0, 200.0])
+@pytest.mark.parametrize("precision", [B.FP64, B.MIXED])
+def test_stiff_step(tau, precision):
+    """A large time step makes the rows barely diagonally dominant (tau = 200:
+    the off-diagonal weight of a row is ~0.999 of its diagonal) and SOR slow.
+    The FP64 step and the mixed step (BF16 coefficients, refined in FP64) both
+    reach their rule and lie within the sum of the two tolerances times
+    ||b||_2 of the oracle converged to 1e-13 (||A^-1||_inf <= 1)."""
+    n = (12, 10, 8, 4)
+    rng = np.random.default_rng(77)
+    G = rng.uniform(0.05, 1, size=(4,) + B.padded_shape(n))
+    w = np.zeros(B.padded_shape(n))
+    w[1:-1, 1:-1, 1:-1, 1:-1] = rng.uniform(0, 1, size=B.interior_shape(n))
+    ref = orc.step(n, G, w, None, None, orc.StepParams(tau=tau, omega=1.9, tol=1e-13, rescale=False), orc.RB)
+    assert ref["status"] == 0
+    tol = 1e-11
+    sp = B.StepParams(tau=tau, omega=1.9, tol=tol, max_iter=200000, rescale=False, precision=precision,
+                      refine_tol=tol, inner_sweeps=20)
+    u = T(w)
+    r = B.step(n, 1.0, T(G), None, 0, None, u, sp, B.alloc_workspace(n, 0, precision))
+    assert r["status"] == 0 and r["rel_res"] <= tol, r
+    err = np.abs(H(u) - ref["u_resc"]).max()
+    assert err <= (tol + 1e-13) * r["bnorm"] * (1 + 1e-6), (err, r)
+
+
 # ---------------------------------------------------------------------- step
 
 
