@@ -160,7 +160,6 @@ class PlainServer:
     def __init__(self, pp: B.PrepareParams, sp: B.StepParams, steps=20, v=1.0, R=0.0):
         assert sp.precision == B.FP64
         self.pp, self.sp, self.steps, self.v, self.R = pp, sp, steps, v, R
-        self.shared = _Shared(1)
 
     def run(self, windows, realtime=True, log=None, max_seconds=None):
         import torch
