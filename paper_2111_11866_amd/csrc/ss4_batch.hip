@@ -51,43 +51,66 @@ __global__ void kb_init(BTable T, double tol, int max_outer)
     }
 }
 
-// Assembly of every job (one thread per padded cell), writing the flat layout.
-__global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
+// Colour-split copy of every padded cell of u^{resc;n-1} (its ghost layer is
+// the Dirichlet data) into x, one thread per padded cell.
+__global__ __launch_bounds__(kBlock) void kb_split_u(BTable T)
 {
     for_runs(T.asm_start, nullptr, T.n_jobs, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
         const BJob J = T.jobs[jb];
         SS4_GLOBAL const double* u = gbl(static_cast<const double*>(J.u));
-        SS4_GLOBAL const double* G = gbl(J.G);
         SS4_GLOBAL double* xr = gbl(J.xr);
         SS4_GLOBAL double* xb = gbl(J.xb);
+        const uint32_t npad = (uint32_t)J.npad;
+        for (uint32_t item = i0; item < i1; item += step) {
+            const uint32_t p = item * kItem + threadIdx.x;
+            if (p >= npad) continue;
+            const uint32_t prow = fdiv(p, J.mg_p1);
+            const int i = (int)(p - prow * (uint32_t)J.p1);
+            const uint32_t t2 = fdiv(prow, J.mg_p2);
+            const int j = (int)(prow - t2 * (uint32_t)J.p2);
+            const uint32_t t3 = fdiv(t2, J.mg_p3);
+            const int k = (int)(t2 - t3 * (uint32_t)J.p3);
+            const int l = (int)t3;
+            const uint32_t us = prow * (uint32_t)J.rsu + 1 + ((i - 1) >> 1);
+            if (((i + j + k + l) & 1) == 0) xr[us] = u[p];
+            else xb[us] = u[p];
+        }
+    });
+}
+
+// Assembly of every job, one thread per interior cell (no lane of a wave
+// idles on a ghost cell), writing the flat layout.
+__global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
+{
+    for_runs(T.int_start, nullptr, T.n_jobs, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
+        const BJob J = T.jobs[jb];
+        SS4_GLOBAL const double* u = gbl(static_cast<const double*>(J.u));
+        SS4_GLOBAL const double* G = gbl(J.G);
         SS4_GLOBAL double* coef = gbl(J.coef);
         SS4_GLOBAL u32x4* c16 = gbl(reinterpret_cast<u32x4*>(J.c16));
         SS4_GLOBAL float* rf = gbl(J.rf);
         SS4_GLOBAL double* pa = gbl(J.part_a);
         SS4_GLOBAL double* pb = gbl(J.part_b);
         const uint32_t npad = (uint32_t)J.npad;
+        const uint32_t nint = (uint32_t)J.nint;
         const uint32_t sd[4] = {1u, (uint32_t)J.p1, (uint32_t)J.p1 * J.p2, (uint32_t)J.p1 * J.p2 * J.p3};
         const int nn[4] = {J.n1, J.n2, J.n3, J.n4};
         for (uint32_t item = i0; item < i1; item += step) {
-            const uint32_t p = item * kItem + threadIdx.x;
+            const uint32_t qi = item * kItem + threadIdx.x;
             double acc_b = 0.0, acc_r = 0.0;
-            if (p < npad) {
-                const uint32_t prow = fdiv(p, J.mg_p1);
-                const int i = (int)(p - prow * (uint32_t)J.p1);
-                const uint32_t t2 = fdiv(prow, J.mg_p2);
-                const int j = (int)(prow - t2 * (uint32_t)J.p2);
-                const uint32_t t3 = fdiv(t2, J.mg_p3);
-                const int k = (int)(t2 - t3 * (uint32_t)J.p3);
-                const int l = (int)t3;
+            if (qi < nint) {
+                const uint32_t r1 = fdiv(qi, J.mg_n1);
+                const int i = (int)(qi - r1 * (uint32_t)J.n1) + 1;
+                const uint32_t r2 = fdiv(r1, J.mg_n2);
+                const int j = (int)(r1 - r2 * (uint32_t)J.n2) + 1;
+                const uint32_t r3 = fdiv(r2, J.mg_n3);
+                const int k = (int)(r2 - r3 * (uint32_t)J.n3) + 1;
+                const int l = (int)r3 + 1;
+                const uint32_t p = (((uint32_t)l * J.p3 + (uint32_t)k) * J.p2 + (uint32_t)j) * J.p1 + (uint32_t)i;
                 const int colour = (i + j + k + l) & 1;
                 const int m = (i - 1) >> 1;
                 const double w0 = u[p];
-                const uint32_t us = prow * (uint32_t)J.rsu + 1 + m;
-                if (colour == 0) xr[us] = w0;
-                else xb[us] = w0;
-                const bool inside =
-                    i >= 1 && i <= J.n1 && j >= 1 && j <= J.n2 && k >= 1 && k <= J.n3 && l >= 1 && l <= J.n4;
-                if (inside) {
+                {
                     const int idx[4] = {i, j, k, l};
                     double wm[4], wp[4], q[8];
 #pragma unroll
@@ -167,8 +190,9 @@ __global__ __launch_bounds__(kBlock) void kb_assemble_decide(BTable T)
     __shared__ double lds[4];
     for (int jb = blockIdx.x; jb < T.n_jobs; jb += gridDim.x) {
         const BJob& J = T.jobs[jb];
-        const double B2 = sum_partials(J.part_a, (int)(kWaves * J.nip), lds);
-        const double R2 = sum_partials(J.part_b, (int)(kWaves * J.nip), lds);
+        const int np = (int)(kWaves * ((J.nint + kItem - 1) / kItem));
+        const double B2 = sum_partials(J.part_a, np, lds);
+        const double R2 = sum_partials(J.part_b, np, lds);
         if (threadIdx.x == 0) {
             Ctrl* C = J.C;
             C->bn = sqrt(B2);
@@ -570,7 +594,7 @@ size_t batch_job_bytes(const int32_t n[4], int32_t nc)
 size_t batch_table_bytes(int32_t n_jobs)
 {
     const size_t nj = (size_t)(n_jobs > 0 ? n_jobs : 1);
-    return al256(sizeof(BJob) * nj) + al256(sizeof(Ctrl) * nj) + 7 * al256(sizeof(int64_t) * (nj + 1)) +
+    return al256(sizeof(BJob) * nj) + al256(sizeof(Ctrl) * nj) + 8 * al256(sizeof(int64_t) * (nj + 1)) +
            al256(sizeof(int) * nj) + 256;
 }
 
@@ -658,8 +682,9 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
 {
     // host-side descriptors
     std::vector<BJob> hj(n_jobs);
-    std::vector<int64_t> asm_start(n_jobs + 1), col_start(n_jobs + 1), both_start(n_jobs + 1), ball_start(n_jobs + 1);
-    asm_start[0] = col_start[0] = both_start[0] = ball_start[0] = 0;
+    std::vector<int64_t> asm_start(n_jobs + 1), int_start(n_jobs + 1), col_start(n_jobs + 1), both_start(n_jobs + 1),
+        ball_start(n_jobs + 1);
+    asm_start[0] = int_start[0] = col_start[0] = both_start[0] = ball_start[0] = 0;
     for (int q = 0; q < n_jobs; ++q) {
         const subsurf4d_batch_job& bj = jobs[q];
         BJob J;
@@ -674,6 +699,7 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
         J.centres = bj.centres;
         hj[q] = J;
         asm_start[q + 1] = asm_start[q] + J.nip;
+        int_start[q + 1] = int_start[q] + (J.nint + kItem - 1) / kItem;
         col_start[q + 1] = col_start[q] + J.nit;
         both_start[q + 1] = both_start[q] + 2 * J.nit;
         ball_start[q + 1] = ball_start[q] + J.nc;
@@ -688,6 +714,7 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
     T.jobs = reinterpret_cast<BJob*>(tb + off); off += al256(sizeof(BJob) * n_jobs);
     T.out = reinterpret_cast<Ctrl*>(tb + off); off += al256(sizeof(Ctrl) * n_jobs);
     T.asm_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
+    T.int_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
     T.col_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
     T.both_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
     T.ball_start = reinterpret_cast<int64_t*>(tb + off); off += al256(sizeof(int64_t) * (n_jobs + 1));
@@ -704,6 +731,7 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
     T.omega = (float)sp.omega;
     SS4_HIP(hipMemcpyAsync(T.jobs, hj.data(), sizeof(BJob) * n_jobs, hipMemcpyHostToDevice, s));
     SS4_HIP(hipMemcpyAsync(T.asm_start, asm_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
+    SS4_HIP(hipMemcpyAsync(T.int_start, int_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
     SS4_HIP(hipMemcpyAsync(T.col_start, col_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
     SS4_HIP(hipMemcpyAsync(T.both_start, both_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
     SS4_HIP(hipMemcpyAsync(T.ball_start, ball_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
@@ -715,6 +743,7 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
 
     kb_init<<<(n_jobs + 255) / 256, 256, 0, s>>>(T, sp.refine_tol, T.max_outer);
     const int g_dec = n_jobs < 4096 ? n_jobs : 4096;
+    kb_split_u<<<g_up, kBlock, 0, s>>>(T);
     kb_assemble<<<g_asm, kBlock, 0, s>>>(T);
     kb_assemble_decide<<<g_dec, kBlock, 0, s>>>(T);
     kb_compact<<<1, kScan, 0, s>>>(T);
