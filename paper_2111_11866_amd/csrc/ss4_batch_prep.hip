@@ -338,33 +338,101 @@ __global__ __launch_bounds__(kBlock) void kp_lhe_decide(PTable T)
     }
 }
 
-// SOR half-sweep of colour COLOR on the unfinished systems.
+// SOR half-sweep of colour COLOR on the unfinished systems, with the
+// stopping-rule residual of its rows fused in (the iterate is that of the
+// red-black pass counter p = *T.pass).  The red sweep of pass p evaluates the
+// red rows of iterate p-1, D (ubar - u) before their update, and keeps iterate
+// p-1's red values in R; the black sweep of pass p evaluates the black rows of
+// iterate p, D (1 - omega)(ubar - u_old).  One partial of r^2 per wave and
+// item: red items first, then black items.  A lane takes one cell of the swept
+// colour (flat per-colour numbering q = r*half + m, cell i = 2m + 2 - par).
 template <int COLOR>
 __global__ __launch_bounds__(kBlock) void kp_lhe_sweep(PTable T)
 {
-    // one lane per cell of colour COLOR: a work item is 256 consecutive q of
-    // the colour's flat numbering q = r*half + m (cell i = 2m + 2 - par of
-    // interior row r), so no lane idles on the other colour
     const double a = T.a, om = T.omega, om1 = 1.0 - T.omega;
     for_runs(T.col_start, nullptr, T.n_jobs, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
         const BJob J = T.jobs[jb];
         const bool run0 = !J.C->done, run1 = !J.C2->done;
         if (!run0 && !run1) return;
+        const uint32_t pbase = COLOR ? (uint32_t)J.nit : 0u;
+        for (uint32_t item = i0; item < i1; item += step) {
+            double r0 = 0.0, r1 = 0.0;
+            Cell cc;
+            if (bdecode(J, COLOR, item * kItem + threadIdx.x, cc)) {
+                const ICell c{2 * cc.m + 2 - cc.par, cc.j, cc.k, cc.l};
+                const uint32_t q = ((((uint32_t)c.l - 1) * (uint32_t)J.n3 + ((uint32_t)c.k - 1)) * (uint32_t)J.n2 +
+                                    ((uint32_t)c.j - 1)) * (uint32_t)J.n1 + ((uint32_t)c.i - 1);
+                double D;
+                if (run0) {
+                    const double s = lhe_row(J, a, J.I0, J.S0, q, c, &D);
+                    const double ubar = s / D, uold = J.S0[q];
+                    const double r = COLOR == 0 ? D * (ubar - uold) : D * om1 * (ubar - uold);
+                    r0 = r * r;
+                    if (COLOR == 0) J.R0[q] = uold;
+                    J.S0[q] = om * ubar + om1 * uold;
+                }
+                if (run1) {
+                    const double s = lhe_row(J, a, J.ITH, J.S1, q, c, &D);
+                    const double ubar = s / D, uold = J.S1[q];
+                    const double r = COLOR == 0 ? D * (ubar - uold) : D * om1 * (ubar - uold);
+                    r1 = r * r;
+                    if (COLOR == 0) J.R1[q] = uold;
+                    J.S1[q] = om * ubar + om1 * uold;
+                }
+            }
+            const double s0 = wave_sum(r0), s1 = wave_sum(r1);
+            if ((threadIdx.x & 63) == 0) {
+                if (run0) J.part_a[(pbase + item) * kWaves + (threadIdx.x >> 6)] = s0;
+                if (run1) J.part_b[(pbase + item) * kWaves + (threadIdx.x >> 6)] = s1;
+            }
+        }
+    });
+}
+
+// Stopping rule of iterate k = pass - 1 >= 1 (between the red and the black
+// sweep of pass k+1): its red rows' partials come from that red sweep, its
+// black rows' from the black sweep of pass k.  One block per job, fixed order.
+__global__ __launch_bounds__(kBlock) void kp_lhe_decide_lag(PTable T)
+{
+    __shared__ double lds[4];
+    const int k = *T.pass - 1;
+    if (k < 1) return;                                      // iterate 0: decided by the full residual
+    for (int jb = blockIdx.x; jb < T.n_jobs; jb += gridDim.x) {
+        const BJob& J = T.jobs[jb];
+        const int np = (int)(kWaves * 2 * J.nit);
+        for (int f = 0; f < 2; ++f) {
+            Ctrl* C = f ? J.C2 : J.C;
+            if (C->done) continue;                          // uniform: read by the whole block
+            const double R2 = sum_partials(f ? J.part_b : J.part_a, np, lds);
+            if (threadIdx.x == 0) {
+                const double R = sqrt(R2);
+                C->rel_res = C->bn > 0.0 ? R / C->bn : R;
+                C->iterations = k;
+                if (!(R2 < INFINITY)) { C->status = SUBSURF4D_ENONFINITE; C->done = 1; }
+                else if (R <= C->tol * C->bn) C->done = 1;
+                else if (k >= C->max_iter) { C->status = SUBSURF4D_NOT_CONVERGED; C->done = 1; }
+                if (C->done) atomicSub(T.active, 1);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// A system decided on iterate k >= 1 at pass k+1, whose red sweep had already
+// moved its red cells on: put iterate k's red values back.
+__global__ __launch_bounds__(kBlock) void kp_lhe_restore(PTable T)
+{
+    for_runs(T.col_start, nullptr, T.n_jobs, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
+        const BJob J = T.jobs[jb];
+        const bool b0 = J.C->iterations >= 1, b1 = J.C2->iterations >= 1;
+        if (!b0 && !b1) return;
         for (uint32_t item = i0; item < i1; item += step) {
             Cell cc;
-            if (!bdecode(J, COLOR, item * kItem + threadIdx.x, cc)) continue;
-            const ICell c{2 * cc.m + 2 - cc.par, cc.j, cc.k, cc.l};
-            const uint32_t q = ((((uint32_t)c.l - 1) * (uint32_t)J.n3 + ((uint32_t)c.k - 1)) * (uint32_t)J.n2 +
-                                ((uint32_t)c.j - 1)) * (uint32_t)J.n1 + ((uint32_t)c.i - 1);
-            double D;
-            if (run0) {
-                const double s = lhe_row(J, a, J.I0, J.S0, q, c, &D);
-                J.S0[q] = om * (s / D) + om1 * J.S0[q];
-            }
-            if (run1) {
-                const double s = lhe_row(J, a, J.ITH, J.S1, q, c, &D);
-                J.S1[q] = om * (s / D) + om1 * J.S1[q];
-            }
+            if (!bdecode(J, 0, item * kItem + threadIdx.x, cc)) continue;
+            const uint32_t q = ((((uint32_t)cc.l - 1) * (uint32_t)J.n3 + ((uint32_t)cc.k - 1)) * (uint32_t)J.n2 +
+                                ((uint32_t)cc.j - 1)) * (uint32_t)J.n1 + (uint32_t)(2 * cc.m + 1 - cc.par);
+            if (b0) J.S0[q] = J.R0[q];
+            if (b1) J.S1[q] = J.R1[q];
         }
     });
 }
@@ -533,9 +601,9 @@ int run_batch_prepare_on(const subsurf4d_batch_prepare_job* jobs, int n_jobs, co
         const subsurf4d_batch_prepare_job& pj = jobs[q];
         BJob J;
         if (int rc = bind_batch_job(pj.grid.n, pj.n_centres, pj.workspace, pj.workspace_bytes, &J)) return rc;
-        // scratch: four interior FP64 fields in the coefficient region
+        // scratch: six interior FP64 fields in the coefficient region
         const size_t coef_bytes = sizeof(double) * 2 * (size_t)J.ntq * kTileVals;
-        if (coef_bytes < 4 * sizeof(double) * (size_t)J.nint) {
+        if (coef_bytes < 6 * sizeof(double) * (size_t)J.nint) {
             set_error("internal: batched preparation scratch does not fit");
             return SUBSURF4D_EDEVICE;
         }
@@ -543,6 +611,8 @@ int run_batch_prepare_on(const subsurf4d_batch_prepare_job* jobs, int n_jobs, co
         J.ITH = J.I0 + J.nint;
         J.S0 = J.ITH + J.nint;
         J.S1 = J.S0 + J.nint;
+        J.R0 = J.S1 + J.nint;
+        J.R1 = J.R0 + J.nint;
         J.inv_h = 1.0 / pj.grid.h;
         J.G = pj.G;
         J.u = pj.u;
@@ -622,11 +692,12 @@ int run_batch_prepare_on(const subsurf4d_batch_prepare_job* jobs, int n_jobs, co
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         SS4_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        // one red-black pass p: red sweep (red rows of iterate p-1), decision
+        // on iterate p-1, black sweep (black rows of iterate p)
         kp_next_pass<<<1, 64, 0, s>>>(T);
         kp_lhe_sweep<0><<<g_cell, kBlock, 0, s>>>(T);
+        kp_lhe_decide_lag<<<g_job, kBlock, 0, s>>>(T);
         kp_lhe_sweep<1><<<g_cell, kBlock, 0, s>>>(T);
-        kp_lhe_residual<<<g_cell, kBlock, 0, s>>>(T);
-        kp_lhe_decide<<<g_job, kBlock, 0, s>>>(T);
         SS4_HIP(hipStreamEndCapture(s, &graph));
         hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         int rc = 0;
@@ -643,17 +714,19 @@ int run_batch_prepare_on(const subsurf4d_batch_prepare_job* jobs, int n_jobs, co
                 e = hipMemcpyAsync(&active, T.active, sizeof(int), hipMemcpyDeviceToHost, s);
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
                 if (e != hipSuccess || active <= 0) break;
-                if (k > pp.smooth_max_iter) {
+                // iterate k is decided at pass k+1, so up to smooth_max_iter + 1 passes
+                if (k > pp.smooth_max_iter + 1) {
                     set_error("internal: batched heat solve ended without a decision");
                     rc = SUBSURF4D_EDEVICE;
                     break;
                 }
-                // iterations past a system's decision leave it untouched
-                for (int c = 0; c < chunk && k <= pp.smooth_max_iter && e == hipSuccess; ++c, ++k)
+                // passes past a system's decision leave it untouched
+                for (int c = 0; c < chunk && k <= pp.smooth_max_iter + 1 && e == hipSuccess; ++c, ++k)
                     e = hipGraphLaunch(exec, s);
                 chunk = chunk < 16 ? chunk * 2 : 16;
             }
             if (e == hipSuccess && rc == 0) {
+                kp_lhe_restore<<<g_cell, kBlock, 0, s>>>(T);
                 kp_gather<<<(n_jobs + 255) / 256, 256, 0, s>>>(T);
                 e = hipMemcpyAsync(hout.data(), T.out, sizeof(int4) * n_jobs, hipMemcpyDeviceToHost, s);
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
