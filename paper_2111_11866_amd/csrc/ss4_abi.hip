@@ -101,6 +101,7 @@ bool plan_workspace(const int32_t n[4], int32_t n_centres, int32_t precision, Ws
     P->ITH = q; q += align256(sizeof(double) * L.nint);
     P->S0 = q; q += align256(sizeof(double) * L.nint);
     P->S1 = q; q += align256(sizeof(double) * L.nint);
+    P->R = q; q += align256(sizeof(double) * L.nint);
     P->prep_bytes = q - off;
 
     P->total = off + (P->step_bytes > P->prep_bytes ? P->step_bytes : P->prep_bytes);

@@ -258,7 +258,8 @@ __global__ __launch_bounds__(kBlock) void kp_lhe_bnorm(PTable T)
     }
 }
 
-// (1 + a n_P) J_P - a sum_{interior nbrs} J_nbr - rhs_P, zero Neumann boundary
+// Row P of the heat system (1 + a n_P) J_P - a sum_{interior nbrs} J_nbr = rhs_P
+// (zero Neumann boundary): returns rhs_P + a sum_nbrs v_nbr and sets *D = 1 + a n_P.
 __device__ __forceinline__ double lhe_row(const BJob& J, double a, const double* rhs, const double* v, uint32_t q,
                                          const ICell& c, double* D)
 {
@@ -340,10 +341,10 @@ __global__ __launch_bounds__(kBlock) void kp_lhe_decide(PTable T)
 
 // SOR half-sweep of colour COLOR on the unfinished systems, with the
 // stopping-rule residual of its rows fused in (the iterate is that of the
-// red-black pass counter p = *T.pass).  The red sweep of pass p evaluates the
-// red rows of iterate p-1, D (ubar - u) before their update, and keeps iterate
-// p-1's red values in R; the black sweep of pass p evaluates the black rows of
-// iterate p, D (1 - omega)(ubar - u_old).  One partial of r^2 per wave and
+// red-black pass counter p = *T.pass).  The red sweep of pass p forms the red
+// rows of iterate p-1, rhs - A J before their update, and keeps iterate p-1's
+// red values in R; the black sweep of pass p forms the black rows of iterate p
+// right after their update.  One partial of r^2 per wave and
 // item: red items first, then black items.  A lane takes one cell of the swept
 // colour (flat per-colour numbering q = r*half + m, cell i = 2m + 2 - par).
 template <int COLOR>
@@ -365,19 +366,19 @@ __global__ __launch_bounds__(kBlock) void kp_lhe_sweep(PTable T)
                 double D;
                 if (run0) {
                     const double s = lhe_row(J, a, J.I0, J.S0, q, c, &D);
-                    const double ubar = s / D, uold = J.S0[q];
-                    const double r = COLOR == 0 ? D * (ubar - uold) : D * om1 * (ubar - uold);
+                    const double uold = J.S0[q], unew = om * (s / D) + om1 * uold;
+                    J.S0[q] = unew;
+                    const double r = s - D * (COLOR == 0 ? uold : unew);
                     r0 = r * r;
                     if (COLOR == 0) J.R0[q] = uold;
-                    J.S0[q] = om * ubar + om1 * uold;
                 }
                 if (run1) {
                     const double s = lhe_row(J, a, J.ITH, J.S1, q, c, &D);
-                    const double ubar = s / D, uold = J.S1[q];
-                    const double r = COLOR == 0 ? D * (ubar - uold) : D * om1 * (ubar - uold);
+                    const double uold = J.S1[q], unew = om * (s / D) + om1 * uold;
+                    J.S1[q] = unew;
+                    const double r = s - D * (COLOR == 0 ? uold : unew);
                     r1 = r * r;
                     if (COLOR == 0) J.R1[q] = uold;
-                    J.S1[q] = om * ubar + om1 * uold;
                 }
             }
             const double s0 = wave_sum(r0), s1 = wave_sum(r1);

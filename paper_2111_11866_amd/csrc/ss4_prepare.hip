@@ -214,16 +214,28 @@ __global__ void k_ball_map(Layout L, const subsurf4d_centre* cs, double r, const
 // (1 + a n_P) J_P - a sum_{interior nbrs} J_nbr = rhs_P, a = tau_s/h^2, zero
 // Neumann boundary (no flux through boundary faces), red-black SOR.
 
+// Half-sweep of colour COLOR in red-black pass p, with the stopping rule's
+// residual fused in.  The red sweep forms the red rows of iterate p-1,
+// rhs - A J before their update (the black cells still hold iterate p-1), and
+// keeps iterate p-1's red values in `saved`; the black sweep forms the black
+// rows of iterate p right after their update (their red neighbours already
+// hold iterate p).  Per-block partials: red rows in part_r, black rows in
+// part_k.  The last block of the red sweep of pass p >= 2 judges iterate p-1;
+// a system stopped there has its red cells put back by k_lhe_restore.
 template <int COLOR>
 __global__ __launch_bounds__(kBlock) void k_lhe_sweep(Layout L, double a, double omega,
                                                       const double* __restrict__ rhs, double* J,
-                                                      const Ctrl* C)
+                                                      double* __restrict__ saved, int p, double* part_r,
+                                                      double* part_k, Ctrl* C)
 {
+    __shared__ double lds[4];
+    __shared__ int flag;
     if (C->done) return;
     const int64_t sy = L.n1, sz = (int64_t)L.n1 * L.n2, st = sz * L.n3;
     // one lane per cell of colour COLOR: h = row*half + m walks the colour's
     // cells (cell i = 2m + 2 - par of the row), so no lane idles
     const int64_t ncq = L.nrow_int * L.half;
+    double acc = 0.0;
     for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < ncq; h += (int64_t)gridDim.x * blockDim.x) {
         const int64_t row = h / L.half;
         const int m = (int)(h - row * L.half);
@@ -246,7 +258,48 @@ __global__ __launch_bounds__(kBlock) void k_lhe_sweep(Layout L, double a, double
         if (l > 1) { s += a * J[q - st]; ++cnt; }
         if (l < L.n4) { s += a * J[q + st]; ++cnt; }
         const double D = 1.0 + a * cnt;
-        J[q] = omega * (s / D) + (1.0 - omega) * J[q];
+        const double uold = J[q];
+        const double unew = omega * (s / D) + (1.0 - omega) * uold;
+        J[q] = unew;
+        const double r = s - D * (COLOR == 0 ? uold : unew);
+        acc += r * r;
+        if (COLOR == 0) saved[q] = uold;
+    }
+    const double bs = block_sum(acc, lds);
+    if (threadIdx.x == 0) (COLOR == 0 ? part_r : part_k)[blockIdx.x] = bs;
+    if (COLOR == 1 || p < 2) return;
+    if (!arrive_last(&C->arrive[3], gridDim.x, &flag)) return;
+    const double R2 = sum_partials(part_r, gridDim.x, lds) + sum_partials(part_k, gridDim.x, lds);
+    if (threadIdx.x == 0) {
+        const int it = p - 1;
+        const double R = sqrt(R2);
+        C->rel_res = C->bn > 0.0 ? R / C->bn : R;
+        C->iterations = it;
+        if (!(R2 < INFINITY)) { C->status = SUBSURF4D_ENONFINITE; C->done = 1; }
+        else if (R <= C->tol * C->bn) C->done = 1;
+        else if (it >= C->max_iter) { C->status = SUBSURF4D_NOT_CONVERGED; C->done = 1; }
+        C->arrive[3] = 0;
+    }
+}
+
+// A solve judged on iterate k >= 1 stopped in the red sweep of pass k+1, which
+// had already moved its red cells on: put iterate k's red values back.
+__global__ __launch_bounds__(kBlock) void k_lhe_restore(Layout L, const double* __restrict__ saved, double* J,
+                                                        const Ctrl* C)
+{
+    if (C->iterations < 1) return;
+    const int64_t ncq = L.nrow_int * L.half;
+    for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < ncq; h += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = h / L.half;
+        const int m = (int)(h - row * L.half);
+        const int j = (int)(row % L.n2) + 1;
+        const int64_t r2 = row / L.n2;
+        const int k = (int)(r2 % L.n3) + 1;
+        const int l = (int)(r2 / L.n3) + 1;
+        const int par = (j + k + l) & 1;
+        if (m >= (par ? (L.n1 + 1) >> 1 : L.n1 >> 1)) continue;
+        const int64_t q = row * L.n1 + (2 * m + 1 - par);
+        J[q] = saved[q];
     }
 }
 
@@ -404,6 +457,7 @@ int lhe_solve(const WsPlan& P, double a, double omega, double tol, int max_iter,
     Ctrl* C = ws_ptr<Ctrl>(ws, P.ctrl);
     double* pa = ws_ptr<double>(ws, P.part_a);
     double* pb = ws_ptr<double>(ws, P.part_b);
+    double* saved = ws_ptr<double>(ws, P.R);
     const int gs = grid_for(L.nrow_int * L.half);
     // the residual's per-block partials fit the workspace's partial arrays
     // (at least kGridCap entries), so it takes a full grid as well
@@ -418,18 +472,20 @@ int lhe_solve(const WsPlan& P, double a, double omega, double tol, int max_iter,
         SS4_HIP(hipMemcpyAsync(&hc, C, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
         SS4_HIP(hipStreamSynchronize(s));
         if (hc.done) break;
-        if (k > max_iter) {
+        // iterate k is judged in pass k+1, so up to max_iter + 1 passes
+        if (k > max_iter + 1) {
             set_error("internal: heat solve ended without a decision");
             return SUBSURF4D_EDEVICE;
         }
-        for (int c = 0; c < chunk && k <= max_iter; ++c, ++k) {
-            k_lhe_sweep<0><<<gs, kBlock, 0, s>>>(L, a, omega, rhs, J, C);
-            k_lhe_sweep<1><<<gs, kBlock, 0, s>>>(L, a, omega, rhs, J, C);
-            k_lhe_residual<<<gr, kBlock, 0, s>>>(L, a, rhs, J, k, pa, pb, C);
+        for (int c = 0; c < chunk && k <= max_iter + 1; ++c, ++k) {
+            k_lhe_sweep<0><<<gs, kBlock, 0, s>>>(L, a, omega, rhs, J, saved, k, pa, pb, C);
+            k_lhe_sweep<1><<<gs, kBlock, 0, s>>>(L, a, omega, rhs, J, saved, k, pa, pb, C);
         }
         SS4_LAUNCHED("lhe sweeps");
         if (chunk < 32) chunk *= 2;
     }
+    k_lhe_restore<<<gs, kBlock, 0, s>>>(L, saved, J, C);
+    SS4_LAUNCHED("lhe restore");
     if (hc.status == SUBSURF4D_ENONFINITE) {
         set_error("non-finite residual in the presmoothing solve");
         return SUBSURF4D_ENONFINITE;

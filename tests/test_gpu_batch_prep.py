@@ -165,3 +165,22 @@ def test_prepare_grid_spacing_single_and_batched():
         assert one.prepare(PP) == 0
         np.testing.assert_array_equal(H(one.owner), prep["owner"])
         assert np.abs(H(one.G) - prep["G"]).max() <= 1e-12
+
+
+@pytest.mark.parametrize("cap", [1, 3])
+def test_batched_prepare_heat_solve_cut_by_max_iter(cap):
+    """A heat solve stopped by its iteration limit returns that iterate with
+    status NOT_CONVERGED: the batched form (which judges iterate k during the
+    next pass and then puts back iterate k's red values) against the
+    single-job form, which stops after iterate k itself."""
+    pp = replace(PP, smooth_max_iter=cap)
+    ims = windows([(26, 24, 25, 4), (31, 22, 24, 3)], seed0=8000)
+    rc, st, jobs = batched(ims, pp=pp)
+    assert rc == B.NOT_CONVERGED and st == [B.NOT_CONVERGED] * len(ims)
+    _, _, full = batched(ims)
+    for im, j, f in zip(ims, jobs, full):
+        one = B.Job(im.n, im.image, im.centres, im.seeds, precision=B.FP64)
+        assert one.prepare(pp) == B.NOT_CONVERGED
+        assert np.abs(H(j.G) - H(one.G)).max() <= 1e-13
+        # the limit did cut the solve short
+        assert np.abs(H(j.G) - H(f.G)).max() > 1e-9
