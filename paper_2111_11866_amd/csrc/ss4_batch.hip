@@ -540,14 +540,13 @@ bool plan_batch_job(const int32_t n[4], int32_t nc, BJob* J, size_t* bytes)
     b.ncq = b.nrow_int * b.half;
     b.ntq = (b.ncq + kTileSlots - 1) / kTileSlots;
     b.nip = (b.npad + kItem - 1) / kItem;
-    auto magic = [](uint32_t d) { return (((uint64_t)1 << 63) + d - 1) / d; };
-    b.mg_half = magic((uint32_t)b.half);
-    b.mg_n1 = magic((uint32_t)n[0]);
-    b.mg_n2 = magic((uint32_t)n[1]);
-    b.mg_n3 = magic((uint32_t)n[2]);
-    b.mg_p1 = magic((uint32_t)b.p1);
-    b.mg_p2 = magic((uint32_t)b.p2);
-    b.mg_p3 = magic((uint32_t)b.p3);
+    b.mg_half = fdiv_magic((uint32_t)b.half);
+    b.mg_n1 = fdiv_magic((uint32_t)n[0]);
+    b.mg_n2 = fdiv_magic((uint32_t)n[1]);
+    b.mg_n3 = fdiv_magic((uint32_t)n[2]);
+    b.mg_p1 = fdiv_magic((uint32_t)b.p1);
+    b.mg_p2 = fdiv_magic((uint32_t)b.p2);
+    b.mg_p3 = fdiv_magic((uint32_t)b.p3);
     b.nit = (b.ncq + kItem - 1) / kItem;
     b.nqf = (int64_t)n[1] * n[2] * b.half;
     b.nitf = (b.nqf + kItem - 1) / kItem;

@@ -93,15 +93,6 @@ __device__ __forceinline__ SS4_GLOBAL T* gbl(T* p) { return (SS4_GLOBAL T*)p; }
 // a class that does not bind to global-address-space references)
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// floor(n / d) for n < 2^31 with M = ceil(2^63 / d): n*M/2^63 exceeds n/d by
-// less than 2^-32, and the fractional part of n/d is at most 1 - 1/d, so the
-// floor is exact for every d < 2^32.
-__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint64_t M)
-{
-    const uint64_t lo = (uint64_t)n * (uint32_t)M;
-    const uint64_t mid = (uint64_t)n * (uint32_t)(M >> 32) + (lo >> 32);
-    return (uint32_t)(mid >> 31);
-}
 
 __device__ __forceinline__ int find_job(const int64_t* start, int n, int64_t w)
 {

@@ -458,56 +458,38 @@ __global__ __launch_bounds__(kBlock) void kp_lhe_rotate(PTable T)
     });
 }
 
-// interior value with clamped indices (image outside the box = nearest value)
-__device__ __forceinline__ double bclamped(const BJob& J, const double* v, int i, int j, int k, int l)
-{
-    return v[biidx(J, clampi(i, 1, J.n1), clampi(j, 1, J.n2), clampi(k, 1, J.n3), clampi(l, 1, J.n4))];
-}
-
-// |reduced-diamond-cell gradient|^2 on the +e_d face of cell (i,j,k,l)
-__device__ double bface_q(const BJob& J, const double* v, int i, int j, int k, int l, int d)
-{
-    int P[4] = {i, j, k, l};
-    int Q[4] = {i, j, k, l};
-    Q[d] += 1;
-    const double vP = bclamped(J, v, P[0], P[1], P[2], P[3]);
-    const double vQ = bclamped(J, v, Q[0], Q[1], Q[2], Q[3]);
-    double g = (vQ - vP) * J.inv_h;
-    double q = g * g;
-    for (int t = 0; t < 4; ++t) {
-        if (t == d) continue;
-        int Pp[4] = {P[0], P[1], P[2], P[3]}, Pm[4] = {P[0], P[1], P[2], P[3]};
-        int Qp[4] = {Q[0], Q[1], Q[2], Q[3]}, Qm[4] = {Q[0], Q[1], Q[2], Q[3]};
-        Pp[t] += 1; Pm[t] -= 1; Qp[t] += 1; Qm[t] -= 1;
-        const double tg = ((bclamped(J, v, Pp[0], Pp[1], Pp[2], Pp[3]) + bclamped(J, v, Qp[0], Qp[1], Qp[2], Qp[3])) -
-                           (bclamped(J, v, Pm[0], Pm[1], Pm[2], Pm[3]) + bclamped(J, v, Qm[0], Qm[1], Qm[2], Qm[3]))) *
-                          (0.25 * J.inv_h);
-        q += tg * tg;
-    }
-    return q;
-}
-
-// G on the 4 "+" faces of every padded cell
+// G on the 4 "+" faces of every padded cell (both images through face_q4)
 __global__ __launch_bounds__(kBlock) void kp_face_g(PTable T, double K, double delta, double vartheta)
 {
     for_runs(T.pad_start, nullptr, T.n_jobs, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
         const BJob J = T.jobs[jb];
         const uint32_t npad = (uint32_t)J.npad;
         double* G = const_cast<double*>(J.G);
+        const int n[4] = {J.n1, J.n2, J.n3, J.n4};
+        const uint32_t stride[4] = {1u, (uint32_t)J.n1, (uint32_t)J.n1 * (uint32_t)J.n2,
+                                    (uint32_t)J.n1 * (uint32_t)J.n2 * (uint32_t)J.n3};
         for (uint32_t item = i0; item < i1; item += step) {
             const uint32_t p = item * kItem + threadIdx.x;
             if (p >= npad) continue;
+            int c[4];
             const uint32_t row = fdiv(p, J.mg_p1);
-            const int i = (int)(p - row * (uint32_t)J.p1);
+            c[0] = (int)(p - row * (uint32_t)J.p1);
             const uint32_t r2 = fdiv(row, J.mg_p2);
-            const int j = (int)(row - r2 * (uint32_t)J.p2);
+            c[1] = (int)(row - r2 * (uint32_t)J.p2);
             const uint32_t r3 = fdiv(r2, J.mg_p3);
-            const int k = (int)(r2 - r3 * (uint32_t)J.p3);
-            const int l = (int)r3;
+            c[2] = (int)(r2 - r3 * (uint32_t)J.p3);
+            c[3] = (int)r3;
+            uint32_t off[4][3];
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+#pragma unroll
+                for (int sh = -1; sh <= 1; ++sh) off[d][sh + 1] = (uint32_t)(clampi(c[d] + sh, 1, n[d]) - 1) * stride[d];
+            double q0[4], q1[4];
+            face_q4(J.S0, off, J.inv_h, q0);
+            face_q4(J.S1, off, J.inv_h, q1);
+#pragma unroll
             for (int d = 0; d < 4; ++d) {
-                const double n0 = sqrt(bface_q(J, J.S0, i, j, k, l, d));
-                const double n1 = sqrt(bface_q(J, J.S1, i, j, k, l, d));
-                const double s = delta * n0 + vartheta * n1;
+                const double s = delta * sqrt(q0[d]) + vartheta * sqrt(q1[d]);
                 G[(uint32_t)d * npad + p] = 1.0 / (1.0 + K * (s * s));
             }
         }

@@ -143,4 +143,47 @@ private:
     double ms_ = 0.0;
 };
 
+// floor(n / d) for n < 2^31 with M = fdiv_magic(d) = ceil(2^63 / d): n*M/2^63
+// exceeds n/d by less than 2^-32, and the fractional part of n/d is at most
+// 1 - 1/d, so the floor is exact for every d < 2^32.
+inline uint64_t fdiv_magic(uint32_t d) { return (((uint64_t)1 << 63) + d - 1) / d; }
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, uint64_t M)
+{
+    const uint64_t lo = (uint64_t)n * (uint32_t)M;
+    const uint64_t mid = (uint64_t)n * (uint32_t)(M >> 32) + (lo >> 32);
+    return (uint32_t)(mid >> 31);
+}
+
+// Squared reduced-diamond-cell gradients of v on the four "+" faces of one cell
+// (Sec. 3.2.2: normal difference over h, tangential ones as the mean of the
+// two cells' central differences), with the image taken as its nearest
+// interior value outside the box.  off[d][s + 1] is the offset along axis d of
+// the clamped coordinate c_d + s, s in {-1, 0, 1}; the 27 values the four
+// faces share are loaded once.
+template <typename IDX>
+__device__ __forceinline__ void face_q4(const double* __restrict__ v, const IDX (&off)[4][3], double inv_h,
+                                        double (&q)[4])
+{
+    auto at = [&](int s0, int s1, int s2, int s3) {
+        return v[off[0][s0 + 1] + off[1][s1 + 1] + off[2][s2 + 1] + off[3][s3 + 1]];
+    };
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int e0 = d == 0, e1 = d == 1, e2 = d == 2, e3 = d == 3;
+        const double g = (at(e0, e1, e2, e3) - at(0, 0, 0, 0)) * inv_h;
+        double acc = g * g;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (t == d) continue;
+            const int f0 = t == 0, f1 = t == 1, f2 = t == 2, f3 = t == 3;
+            const double tg = ((at(f0, f1, f2, f3) + at(e0 + f0, e1 + f1, e2 + f2, e3 + f3)) -
+                               (at(-f0, -f1, -f2, -f3) + at(e0 - f0, e1 - f1, e2 - f2, e3 - f3))) *
+                              (0.25 * inv_h);
+            acc += tg * tg;
+        }
+        q[d] = acc;
+    }
+}
+
 }  // namespace ss4

@@ -3,6 +3,7 @@
 // local rescaling (Sec. 3.1 and Sec. 3.2.2 of the paper).
 #include <climits>
 #include <cmath>
+#include <type_traits>
 
 #include "ss4_internal.hpp"
 
@@ -214,6 +215,45 @@ __global__ void k_ball_map(Layout L, const subsurf4d_centre* cs, double r, const
 // (1 + a n_P) J_P - a sum_{interior nbrs} J_nbr = rhs_P, a = tau_s/h^2, zero
 // Neumann boundary (no flux through boundary faces), red-black SOR.
 
+// Magic constants of the index divisions of the heat kernels: grids whose flat
+// indices stay below 2^31 (NARROW) decode cells with 32-bit multiplies instead
+// of 64-bit divisions, which bound these kernels by ALU work.
+struct HeatDiv { uint64_t half, n1, n2, n3; };
+
+// Cell (i, j, k, l) and interior index q of colour COLOR's flat index
+// h = row*half + m (cell i = 2m + 2 - par of the row); false where the row has
+// no such cell (a row of odd length holds one cell more of one colour).
+template <int COLOR, bool NARROW>
+__device__ __forceinline__ bool heat_cell(const Layout& L, const HeatDiv& M, int64_t h, int64_t& q, int& i, int& j,
+                                          int& k, int& l)
+{
+    int64_t row;
+    int m;
+    if (NARROW) {
+        const uint32_t hh = (uint32_t)h;
+        const uint32_t r = fdiv(hh, M.half);
+        m = (int)(hh - r * (uint32_t)L.half);
+        const uint32_t r2 = fdiv(r, M.n2);
+        j = (int)(r - r2 * (uint32_t)L.n2) + 1;
+        const uint32_t r3 = fdiv(r2, M.n3);
+        k = (int)(r2 - r3 * (uint32_t)L.n3) + 1;
+        l = (int)r3 + 1;
+        row = r;
+    } else {
+        row = h / L.half;
+        m = (int)(h - row * L.half);
+        j = (int)(row % L.n2) + 1;
+        const int64_t r2 = row / L.n2;
+        k = (int)(r2 % L.n3) + 1;
+        l = (int)(r2 / L.n3) + 1;
+    }
+    const int par = (COLOR + j + k + l) & 1;
+    if (m >= (par ? (L.n1 + 1) >> 1 : L.n1 >> 1)) return false;
+    i = 2 * m + 2 - par;
+    q = NARROW ? (int64_t)((uint32_t)row * (uint32_t)L.n1 + (uint32_t)(i - 1)) : row * L.n1 + (i - 1);
+    return true;
+}
+
 // Half-sweep of colour COLOR in red-black pass p, with the stopping rule's
 // residual fused in.  The red sweep forms the red rows of iterate p-1,
 // rhs - A J before their update (the black cells still hold iterate p-1), and
@@ -222,8 +262,8 @@ __global__ void k_ball_map(Layout L, const subsurf4d_centre* cs, double r, const
 // hold iterate p).  Per-block partials: red rows in part_r, black rows in
 // part_k.  The last block of the red sweep of pass p >= 2 judges iterate p-1;
 // a system stopped there has its red cells put back by k_lhe_restore.
-template <int COLOR>
-__global__ __launch_bounds__(kBlock) void k_lhe_sweep(Layout L, double a, double omega,
+template <int COLOR, bool NARROW>
+__global__ __launch_bounds__(kBlock) void k_lhe_sweep(Layout L, HeatDiv M, double a, double omega,
                                                       const double* __restrict__ rhs, double* J,
                                                       double* __restrict__ saved, int p, double* part_r,
                                                       double* part_k, Ctrl* C)
@@ -232,21 +272,13 @@ __global__ __launch_bounds__(kBlock) void k_lhe_sweep(Layout L, double a, double
     __shared__ int flag;
     if (C->done) return;
     const int64_t sy = L.n1, sz = (int64_t)L.n1 * L.n2, st = sz * L.n3;
-    // one lane per cell of colour COLOR: h = row*half + m walks the colour's
-    // cells (cell i = 2m + 2 - par of the row), so no lane idles
+    // one lane per cell of colour COLOR, so no lane idles on the other colour
     const int64_t ncq = L.nrow_int * L.half;
     double acc = 0.0;
     for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < ncq; h += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t row = h / L.half;
-        const int m = (int)(h - row * L.half);
-        const int j = (int)(row % L.n2) + 1;
-        const int64_t r2 = row / L.n2;
-        const int k = (int)(r2 % L.n3) + 1;
-        const int l = (int)(r2 / L.n3) + 1;
-        const int par = (COLOR + j + k + l) & 1;
-        if (m >= (par ? (L.n1 + 1) >> 1 : L.n1 >> 1)) continue;
-        const int i = 2 * m + 2 - par;
-        const int64_t q = row * L.n1 + (i - 1);
+        int64_t q;
+        int i, j, k, l;
+        if (!heat_cell<COLOR, NARROW>(L, M, h, q, i, j, k, l)) continue;
         double s = rhs[q];
         int cnt = 0;
         if (i > 1) { s += a * J[q - 1]; ++cnt; }
@@ -284,28 +316,23 @@ __global__ __launch_bounds__(kBlock) void k_lhe_sweep(Layout L, double a, double
 
 // A solve judged on iterate k >= 1 stopped in the red sweep of pass k+1, which
 // had already moved its red cells on: put iterate k's red values back.
-__global__ __launch_bounds__(kBlock) void k_lhe_restore(Layout L, const double* __restrict__ saved, double* J,
-                                                        const Ctrl* C)
+template <bool NARROW>
+__global__ __launch_bounds__(kBlock) void k_lhe_restore(Layout L, HeatDiv M, const double* __restrict__ saved,
+                                                        double* J, const Ctrl* C)
 {
     if (C->iterations < 1) return;
     const int64_t ncq = L.nrow_int * L.half;
     for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < ncq; h += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t row = h / L.half;
-        const int m = (int)(h - row * L.half);
-        const int j = (int)(row % L.n2) + 1;
-        const int64_t r2 = row / L.n2;
-        const int k = (int)(r2 % L.n3) + 1;
-        const int l = (int)(r2 / L.n3) + 1;
-        const int par = (j + k + l) & 1;
-        if (m >= (par ? (L.n1 + 1) >> 1 : L.n1 >> 1)) continue;
-        const int64_t q = row * L.n1 + (2 * m + 1 - par);
-        J[q] = saved[q];
+        int64_t q;
+        int i, j, k, l;
+        if (heat_cell<0, NARROW>(L, M, h, q, i, j, k, l)) J[q] = saved[q];
     }
 }
 
 // Residual ||rhs - A J||_2 (and ||rhs||_2 at k = 0); the last block applies the
 // stopping rule of the heat solve.
-__global__ __launch_bounds__(kBlock) void k_lhe_residual(Layout L, double a, const double* __restrict__ rhs,
+template <bool NARROW>
+__global__ __launch_bounds__(kBlock) void k_lhe_residual(Layout L, HeatDiv M, double a, const double* __restrict__ rhs,
                                                          const double* __restrict__ J, int k, double* part_r,
                                                          double* part_b, Ctrl* C)
 {
@@ -315,12 +342,24 @@ __global__ __launch_bounds__(kBlock) void k_lhe_residual(Layout L, double a, con
     const int64_t sy = L.n1, sz = (int64_t)L.n1 * L.n2, st = sz * L.n3;
     double ar = 0.0, ab = 0.0;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < L.nint; q += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(q % L.n1) + 1;
-        const int64_t row = q / L.n1;
-        const int j = (int)(row % L.n2) + 1;
-        const int64_t r2 = row / L.n2;
-        const int kk = (int)(r2 % L.n3) + 1;
-        const int l = (int)(r2 / L.n3) + 1;
+        int i, j, kk, l;
+        if (NARROW) {
+            const uint32_t qq = (uint32_t)q;
+            const uint32_t r = fdiv(qq, M.n1);
+            i = (int)(qq - r * (uint32_t)L.n1) + 1;
+            const uint32_t r2 = fdiv(r, M.n2);
+            j = (int)(r - r2 * (uint32_t)L.n2) + 1;
+            const uint32_t r3 = fdiv(r2, M.n3);
+            kk = (int)(r2 - r3 * (uint32_t)L.n3) + 1;
+            l = (int)r3 + 1;
+        } else {
+            i = (int)(q % L.n1) + 1;
+            const int64_t row = q / L.n1;
+            j = (int)(row % L.n2) + 1;
+            const int64_t r2 = row / L.n2;
+            kk = (int)(r2 % L.n3) + 1;
+            l = (int)(r2 / L.n3) + 1;
+        }
         double s = rhs[q];
         int cnt = 0;
         if (i > 1) { s += a * J[q - 1]; ++cnt; }
@@ -355,51 +394,48 @@ __global__ __launch_bounds__(kBlock) void k_lhe_residual(Layout L, double a, con
 
 // --------------------------------------------------------- edge detector G
 
-// interior array read with clamped indices (image outside the box = nearest value)
-__device__ __forceinline__ double clamped(const Layout& L, const double* v, int i, int j, int k, int l)
+// G on the 4 "+" faces of every padded cell.  Both images are read through
+// face_q4; NARROW grids (fewer than 2^31 padded cells) decode with 32-bit
+// multiplies and index with 32-bit offsets.
+template <bool NARROW>
+__global__ __launch_bounds__(kBlock) void k_face_g(Layout L, uint64_t mp1, uint64_t mp2, uint64_t mp3, double inv_h,
+                                                   double K, double delta, double vartheta,
+                                                   const double* __restrict__ S0, const double* __restrict__ S1,
+                                                   double* __restrict__ G)
 {
-    return v[iidx(L, clampi(i, 1, L.n1), clampi(j, 1, L.n2), clampi(k, 1, L.n3), clampi(l, 1, L.n4))];
-}
-
-// |reduced-diamond-cell gradient|^2 on the +e_d face of cell (i,j,k,l)
-__device__ double face_q_clamped(const Layout& L, const double* v, int i, int j, int k, int l, int d,
-                                 double inv_h)
-{
-    int P[4] = {i, j, k, l};
-    int Q[4] = {i, j, k, l};
-    Q[d] += 1;
-    const double vP = clamped(L, v, P[0], P[1], P[2], P[3]);
-    const double vQ = clamped(L, v, Q[0], Q[1], Q[2], Q[3]);
-    double g = (vQ - vP) * inv_h;
-    double q = g * g;
-    for (int t = 0; t < 4; ++t) {
-        if (t == d) continue;
-        int Pp[4] = {P[0], P[1], P[2], P[3]}, Pm[4] = {P[0], P[1], P[2], P[3]};
-        int Qp[4] = {Q[0], Q[1], Q[2], Q[3]}, Qm[4] = {Q[0], Q[1], Q[2], Q[3]};
-        Pp[t] += 1; Pm[t] -= 1; Qp[t] += 1; Qm[t] -= 1;
-        const double tg = ((clamped(L, v, Pp[0], Pp[1], Pp[2], Pp[3]) + clamped(L, v, Qp[0], Qp[1], Qp[2], Qp[3])) -
-                           (clamped(L, v, Pm[0], Pm[1], Pm[2], Pm[3]) + clamped(L, v, Qm[0], Qm[1], Qm[2], Qm[3]))) *
-                          (0.25 * inv_h);
-        q += tg * tg;
-    }
-    return q;
-}
-
-__global__ __launch_bounds__(kBlock) void k_face_g(Layout L, double inv_h, double K, double delta,
-                                                   double vartheta, const double* S0, const double* S1,
-                                                   double* G)
-{
+    using IDX = typename std::conditional<NARROW, uint32_t, int64_t>::type;
+    const int n[4] = {L.n1, L.n2, L.n3, L.n4};
+    const IDX stride[4] = {1, (IDX)L.n1, (IDX)L.n1 * (IDX)L.n2, (IDX)L.n1 * (IDX)L.n2 * (IDX)L.n3};
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < L.npad; p += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(p % L.p1);
-        const int64_t row = p / L.p1;
-        const int j = (int)(row % L.p2);
-        const int64_t r2 = row / L.p2;
-        const int k = (int)(r2 % L.p3);
-        const int l = (int)(r2 / L.p3);
+        int c[4];
+        if (NARROW) {
+            const uint32_t pp = (uint32_t)p;
+            const uint32_t row = fdiv(pp, mp1);
+            c[0] = (int)(pp - row * (uint32_t)L.p1);
+            const uint32_t r2 = fdiv(row, mp2);
+            c[1] = (int)(row - r2 * (uint32_t)L.p2);
+            const uint32_t r3 = fdiv(r2, mp3);
+            c[2] = (int)(r2 - r3 * (uint32_t)L.p3);
+            c[3] = (int)r3;
+        } else {
+            c[0] = (int)(p % L.p1);
+            const int64_t row = p / L.p1;
+            c[1] = (int)(row % L.p2);
+            const int64_t r2 = row / L.p2;
+            c[2] = (int)(r2 % L.p3);
+            c[3] = (int)(r2 / L.p3);
+        }
+        IDX off[4][3];
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+#pragma unroll
+            for (int sh = -1; sh <= 1; ++sh) off[d][sh + 1] = (IDX)(clampi(c[d] + sh, 1, n[d]) - 1) * stride[d];
+        double q0[4], q1[4];
+        face_q4(S0, off, inv_h, q0);
+        face_q4(S1, off, inv_h, q1);
+#pragma unroll
         for (int d = 0; d < 4; ++d) {
-            const double n0 = sqrt(face_q_clamped(L, S0, i, j, k, l, d, inv_h));
-            const double n1 = sqrt(face_q_clamped(L, S1, i, j, k, l, d, inv_h));
-            const double s = delta * n0 + vartheta * n1;
+            const double s = delta * sqrt(q0[d]) + vartheta * sqrt(q1[d]);
             G[(int64_t)d * L.npad + p] = 1.0 / (1.0 + K * (s * s));
         }
     }
@@ -450,8 +486,9 @@ __global__ void k_init_u_scatter(Layout L, const subsurf4d_centre* seeds, double
     }
 }
 
-int lhe_solve(const WsPlan& P, double a, double omega, double tol, int max_iter, const double* rhs,
-              double* J, void* ws, hipStream_t s, int* status)
+template <bool NARROW>
+int lhe_solve_t(const WsPlan& P, double a, double omega, double tol, int max_iter, const double* rhs,
+                double* J, void* ws, hipStream_t s, int* status)
 {
     const Layout& L = P.L;
     Ctrl* C = ws_ptr<Ctrl>(ws, P.ctrl);
@@ -462,9 +499,11 @@ int lhe_solve(const WsPlan& P, double a, double omega, double tol, int max_iter,
     // the residual's per-block partials fit the workspace's partial arrays
     // (at least kGridCap entries), so it takes a full grid as well
     const int gr = grid_for(L.nint);
+    const HeatDiv M{fdiv_magic((uint32_t)L.half), fdiv_magic((uint32_t)L.n1), fdiv_magic((uint32_t)L.n2),
+                    fdiv_magic((uint32_t)L.n3)};
     k_copy_f64<<<grid_for(L.nint), kBlock, 0, s>>>(rhs, J, L.nint);
     k_ctrl_init<<<1, 64, 0, s>>>(C, tol, max_iter);
-    k_lhe_residual<<<gr, kBlock, 0, s>>>(L, a, rhs, J, 0, pa, pb, C);
+    k_lhe_residual<NARROW><<<gr, kBlock, 0, s>>>(L, M, a, rhs, J, 0, pa, pb, C);
     SS4_LAUNCHED("lhe residual");
     Ctrl hc;
     int k = 1, chunk = 4;
@@ -478,13 +517,13 @@ int lhe_solve(const WsPlan& P, double a, double omega, double tol, int max_iter,
             return SUBSURF4D_EDEVICE;
         }
         for (int c = 0; c < chunk && k <= max_iter + 1; ++c, ++k) {
-            k_lhe_sweep<0><<<gs, kBlock, 0, s>>>(L, a, omega, rhs, J, saved, k, pa, pb, C);
-            k_lhe_sweep<1><<<gs, kBlock, 0, s>>>(L, a, omega, rhs, J, saved, k, pa, pb, C);
+            k_lhe_sweep<0, NARROW><<<gs, kBlock, 0, s>>>(L, M, a, omega, rhs, J, saved, k, pa, pb, C);
+            k_lhe_sweep<1, NARROW><<<gs, kBlock, 0, s>>>(L, M, a, omega, rhs, J, saved, k, pa, pb, C);
         }
         SS4_LAUNCHED("lhe sweeps");
         if (chunk < 32) chunk *= 2;
     }
-    k_lhe_restore<<<gs, kBlock, 0, s>>>(L, saved, J, C);
+    k_lhe_restore<NARROW><<<gs, kBlock, 0, s>>>(L, M, saved, J, C);
     SS4_LAUNCHED("lhe restore");
     if (hc.status == SUBSURF4D_ENONFINITE) {
         set_error("non-finite residual in the presmoothing solve");
@@ -492,6 +531,15 @@ int lhe_solve(const WsPlan& P, double a, double omega, double tol, int max_iter,
     }
     if (hc.status == SUBSURF4D_NOT_CONVERGED) *status = SUBSURF4D_NOT_CONVERGED;
     return 0;
+}
+
+int lhe_solve(const WsPlan& P, double a, double omega, double tol, int max_iter, const double* rhs,
+              double* J, void* ws, hipStream_t s, int* status)
+{
+    const Layout& L = P.L;
+    const bool narrow = L.nrow_int * L.half < ((int64_t)1 << 31) && L.nint < ((int64_t)1 << 31);
+    return narrow ? lhe_solve_t<true>(P, a, omega, tol, max_iter, rhs, J, ws, s, status)
+                  : lhe_solve_t<false>(P, a, omega, tol, max_iter, rhs, J, ws, s, status);
 }
 
 }  // namespace
@@ -543,7 +591,13 @@ int run_prepare(const WsPlan& P, double h, const void* image, int dtype, const s
         double* t0 = src0; src0 = dst0; dst0 = t0;
         double* t1 = src1; src1 = dst1; dst1 = t1;
     }
-    k_face_g<<<grid_for(L.npad), kBlock, 0, s>>>(L, 1.0 / h, pp.K, pp.delta, pp.vartheta, src0, src1, G);
+    const uint64_t mp1 = fdiv_magic((uint32_t)L.p1), mp2 = fdiv_magic((uint32_t)L.p2), mp3 = fdiv_magic((uint32_t)L.p3);
+    if (L.npad < ((int64_t)1 << 31))
+        k_face_g<true><<<grid_for(L.npad), kBlock, 0, s>>>(L, mp1, mp2, mp3, 1.0 / h, pp.K, pp.delta, pp.vartheta,
+                                                           src0, src1, G);
+    else
+        k_face_g<false><<<grid_for(L.npad), kBlock, 0, s>>>(L, mp1, mp2, mp3, 1.0 / h, pp.K, pp.delta, pp.vartheta,
+                                                            src0, src1, G);
     SS4_LAUNCHED("prepare: face G");
     return status;
 }
