@@ -101,7 +101,10 @@ bool plan_workspace(const int32_t n[4], int32_t n_centres, int32_t precision, Ws
     P->ITH = q; q += align256(sizeof(double) * L.nint);
     P->S0 = q; q += align256(sizeof(double) * L.nint);
     P->S1 = q; q += align256(sizeof(double) * L.nint);
-    P->R = q; q += align256(sizeof(double) * L.nint);
+    const int64_t ncq = L.nrow_int * L.half;                        // cells of one colour, split numbering
+    P->HR = q; q += align256(sizeof(double) * 2 * ncq);
+    P->HJ = q; q += align256(sizeof(double) * 2 * ncq);
+    P->R = q; q += align256(sizeof(double) * ncq);
     P->prep_bytes = q - off;
 
     P->total = off + (P->step_bytes > P->prep_bytes ? P->step_bytes : P->prep_bytes);

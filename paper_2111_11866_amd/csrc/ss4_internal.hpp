@@ -21,7 +21,8 @@ struct WsPlan {
     // mixed precision (inside the step region)
     size_t coef16 = 0, rf32 = 0, dred = 0, dblack = 0;
     // preparation
-    size_t I0 = 0, ITH = 0, S0 = 0, S1 = 0, R = 0;   // R: red values kept by the heat sweeps
+    size_t I0 = 0, ITH = 0, S0 = 0, S1 = 0;
+    size_t HR = 0, HJ = 0, R = 0;   // heat solve: colour-split rhs and iterate, red values kept by the sweeps
     size_t step_bytes = 0, prep_bytes = 0, total = 0;
 };
 

@@ -254,14 +254,48 @@ __device__ __forceinline__ bool heat_cell(const Layout& L, const HeatDiv& M, int
     return true;
 }
 
-// Half-sweep of colour COLOR in red-black pass p, with the stopping rule's
-// residual fused in.  The red sweep forms the red rows of iterate p-1,
-// rhs - A J before their update (the black cells still hold iterate p-1), and
-// keeps iterate p-1's red values in `saved`; the black sweep forms the black
-// rows of iterate p right after their update (their red neighbours already
-// hold iterate p).  Per-block partials: red rows in part_r, black rows in
-// part_k.  The last block of the red sweep of pass p >= 2 judges iterate p-1;
-// a system stopped there has its red cells put back by k_lhe_restore.
+// The heat solves run on colour-split copies: colour c's cells sit at
+// c*ncq + h, h = row*half + m (cell i = 2m + 2 - par of interior row `row`).
+// Within the other colour's half, a cell's x-neighbours are h - par and
+// h + 1 - par, and its y-, z- and t-neighbours keep m in the adjacent row,
+// plane and frame (h -+ half, half*N2, half*N2*N3), so every access of a
+// sweep is a contiguous run.  Slots past a row's last cell of a colour hold 0
+// and are never read.
+template <int COLOR, bool NARROW>
+__global__ __launch_bounds__(kBlock) void k_heat_split(Layout L, HeatDiv M, const double* __restrict__ nat,
+                                                       double* __restrict__ out0, double* __restrict__ out1)
+{
+    const int64_t ncq = L.nrow_int * L.half;
+    for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < ncq; h += (int64_t)gridDim.x * blockDim.x) {
+        int64_t q;
+        int i, j, k, l;
+        const double v = heat_cell<COLOR, NARROW>(L, M, h, q, i, j, k, l) ? nat[q] : 0.0;
+        out0[COLOR * ncq + h] = v;
+        out1[COLOR * ncq + h] = v;
+    }
+}
+
+template <int COLOR, bool NARROW>
+__global__ __launch_bounds__(kBlock) void k_heat_merge(Layout L, HeatDiv M, const double* __restrict__ split,
+                                                       double* __restrict__ nat)
+{
+    const int64_t ncq = L.nrow_int * L.half;
+    for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < ncq; h += (int64_t)gridDim.x * blockDim.x) {
+        int64_t q;
+        int i, j, k, l;
+        if (heat_cell<COLOR, NARROW>(L, M, h, q, i, j, k, l)) nat[q] = split[COLOR * ncq + h];
+    }
+}
+
+// Half-sweep of colour COLOR in red-black pass p on the split copies, with the
+// stopping rule's residual fused in.  The red sweep forms the red rows of
+// iterate p-1, rhs - A J before their update (the black cells still hold
+// iterate p-1), and keeps iterate p-1's red values in `saved`; the black sweep
+// forms the black rows of iterate p right after their update (their red
+// neighbours already hold iterate p).  Per-block partials: red rows in part_r,
+// black rows in part_k.  The last block of the red sweep of pass p >= 2 judges
+// iterate p-1; a system stopped there has its red cells put back by
+// k_lhe_restore.
 template <int COLOR, bool NARROW>
 __global__ __launch_bounds__(kBlock) void k_lhe_sweep(Layout L, HeatDiv M, double a, double omega,
                                                       const double* __restrict__ rhs, double* J,
@@ -271,31 +305,35 @@ __global__ __launch_bounds__(kBlock) void k_lhe_sweep(Layout L, HeatDiv M, doubl
     __shared__ double lds[4];
     __shared__ int flag;
     if (C->done) return;
-    const int64_t sy = L.n1, sz = (int64_t)L.n1 * L.n2, st = sz * L.n3;
     // one lane per cell of colour COLOR, so no lane idles on the other colour
     const int64_t ncq = L.nrow_int * L.half;
+    const int64_t sy = L.half, sz = (int64_t)L.half * L.n2, st = sz * L.n3;
+    const double* __restrict__ R = rhs + COLOR * ncq;
+    const double* __restrict__ O = J + (1 - COLOR) * ncq;   // the other colour: read only
+    double* __restrict__ W = J + COLOR * ncq;               // this colour: updated
     double acc = 0.0;
     for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < ncq; h += (int64_t)gridDim.x * blockDim.x) {
         int64_t q;
         int i, j, k, l;
         if (!heat_cell<COLOR, NARROW>(L, M, h, q, i, j, k, l)) continue;
-        double s = rhs[q];
+        const int par = (COLOR + j + k + l) & 1;
+        double s = R[h];
         int cnt = 0;
-        if (i > 1) { s += a * J[q - 1]; ++cnt; }
-        if (i < L.n1) { s += a * J[q + 1]; ++cnt; }
-        if (j > 1) { s += a * J[q - sy]; ++cnt; }
-        if (j < L.n2) { s += a * J[q + sy]; ++cnt; }
-        if (k > 1) { s += a * J[q - sz]; ++cnt; }
-        if (k < L.n3) { s += a * J[q + sz]; ++cnt; }
-        if (l > 1) { s += a * J[q - st]; ++cnt; }
-        if (l < L.n4) { s += a * J[q + st]; ++cnt; }
+        if (i > 1) { s += a * O[h - par]; ++cnt; }
+        if (i < L.n1) { s += a * O[h + 1 - par]; ++cnt; }
+        if (j > 1) { s += a * O[h - sy]; ++cnt; }
+        if (j < L.n2) { s += a * O[h + sy]; ++cnt; }
+        if (k > 1) { s += a * O[h - sz]; ++cnt; }
+        if (k < L.n3) { s += a * O[h + sz]; ++cnt; }
+        if (l > 1) { s += a * O[h - st]; ++cnt; }
+        if (l < L.n4) { s += a * O[h + st]; ++cnt; }
         const double D = 1.0 + a * cnt;
-        const double uold = J[q];
+        const double uold = W[h];
         const double unew = omega * (s / D) + (1.0 - omega) * uold;
-        J[q] = unew;
+        W[h] = unew;
         const double r = s - D * (COLOR == 0 ? uold : unew);
         acc += r * r;
-        if (COLOR == 0) saved[q] = uold;
+        if (COLOR == 0) saved[h] = uold;
     }
     const double bs = block_sum(acc, lds);
     if (threadIdx.x == 0) (COLOR == 0 ? part_r : part_k)[blockIdx.x] = bs;
@@ -304,29 +342,25 @@ __global__ __launch_bounds__(kBlock) void k_lhe_sweep(Layout L, HeatDiv M, doubl
     const double R2 = sum_partials(part_r, gridDim.x, lds) + sum_partials(part_k, gridDim.x, lds);
     if (threadIdx.x == 0) {
         const int it = p - 1;
-        const double R = sqrt(R2);
-        C->rel_res = C->bn > 0.0 ? R / C->bn : R;
+        const double Rn = sqrt(R2);
+        C->rel_res = C->bn > 0.0 ? Rn / C->bn : Rn;
         C->iterations = it;
         if (!(R2 < INFINITY)) { C->status = SUBSURF4D_ENONFINITE; C->done = 1; }
-        else if (R <= C->tol * C->bn) C->done = 1;
+        else if (Rn <= C->tol * C->bn) C->done = 1;
         else if (it >= C->max_iter) { C->status = SUBSURF4D_NOT_CONVERGED; C->done = 1; }
         C->arrive[3] = 0;
     }
 }
 
 // A solve judged on iterate k >= 1 stopped in the red sweep of pass k+1, which
-// had already moved its red cells on: put iterate k's red values back.
-template <bool NARROW>
-__global__ __launch_bounds__(kBlock) void k_lhe_restore(Layout L, HeatDiv M, const double* __restrict__ saved,
-                                                        double* J, const Ctrl* C)
+// had already moved its red cells on: put iterate k's red values back (red
+// half of the split copy; the other slots are never read).
+__global__ __launch_bounds__(kBlock) void k_lhe_restore(int64_t ncq, const double* __restrict__ saved,
+                                                        double* __restrict__ J, const Ctrl* C)
 {
     if (C->iterations < 1) return;
-    const int64_t ncq = L.nrow_int * L.half;
-    for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < ncq; h += (int64_t)gridDim.x * blockDim.x) {
-        int64_t q;
-        int i, j, k, l;
-        if (heat_cell<0, NARROW>(L, M, h, q, i, j, k, l)) J[q] = saved[q];
-    }
+    for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < ncq; h += (int64_t)gridDim.x * blockDim.x)
+        J[h] = saved[h];
 }
 
 // Residual ||rhs - A J||_2 (and ||rhs||_2 at k = 0); the last block applies the
@@ -495,6 +529,8 @@ int lhe_solve_t(const WsPlan& P, double a, double omega, double tol, int max_ite
     double* pa = ws_ptr<double>(ws, P.part_a);
     double* pb = ws_ptr<double>(ws, P.part_b);
     double* saved = ws_ptr<double>(ws, P.R);
+    double* HR = ws_ptr<double>(ws, P.HR);       // split right-hand side
+    double* HJ = ws_ptr<double>(ws, P.HJ);       // split iterate
     const int gs = grid_for(L.nrow_int * L.half);
     // the residual's per-block partials fit the workspace's partial arrays
     // (at least kGridCap entries), so it takes a full grid as well
@@ -504,6 +540,8 @@ int lhe_solve_t(const WsPlan& P, double a, double omega, double tol, int max_ite
     k_copy_f64<<<grid_for(L.nint), kBlock, 0, s>>>(rhs, J, L.nint);
     k_ctrl_init<<<1, 64, 0, s>>>(C, tol, max_iter);
     k_lhe_residual<NARROW><<<gr, kBlock, 0, s>>>(L, M, a, rhs, J, 0, pa, pb, C);
+    k_heat_split<0, NARROW><<<gs, kBlock, 0, s>>>(L, M, rhs, HR, HJ);
+    k_heat_split<1, NARROW><<<gs, kBlock, 0, s>>>(L, M, rhs, HR, HJ);
     SS4_LAUNCHED("lhe residual");
     Ctrl hc;
     int k = 1, chunk = 4;
@@ -517,14 +555,16 @@ int lhe_solve_t(const WsPlan& P, double a, double omega, double tol, int max_ite
             return SUBSURF4D_EDEVICE;
         }
         for (int c = 0; c < chunk && k <= max_iter + 1; ++c, ++k) {
-            k_lhe_sweep<0, NARROW><<<gs, kBlock, 0, s>>>(L, M, a, omega, rhs, J, saved, k, pa, pb, C);
-            k_lhe_sweep<1, NARROW><<<gs, kBlock, 0, s>>>(L, M, a, omega, rhs, J, saved, k, pa, pb, C);
+            k_lhe_sweep<0, NARROW><<<gs, kBlock, 0, s>>>(L, M, a, omega, HR, HJ, saved, k, pa, pb, C);
+            k_lhe_sweep<1, NARROW><<<gs, kBlock, 0, s>>>(L, M, a, omega, HR, HJ, saved, k, pa, pb, C);
         }
         SS4_LAUNCHED("lhe sweeps");
         if (chunk < 32) chunk *= 2;
     }
-    k_lhe_restore<NARROW><<<gs, kBlock, 0, s>>>(L, M, saved, J, C);
-    SS4_LAUNCHED("lhe restore");
+    k_lhe_restore<<<gs, kBlock, 0, s>>>(L.nrow_int * L.half, saved, HJ, C);
+    k_heat_merge<0, NARROW><<<gs, kBlock, 0, s>>>(L, M, HJ, J);
+    k_heat_merge<1, NARROW><<<gs, kBlock, 0, s>>>(L, M, HJ, J);
+    SS4_LAUNCHED("lhe restore / merge");
     if (hc.status == SUBSURF4D_ENONFINITE) {
         set_error("non-finite residual in the presmoothing solve");
         return SUBSURF4D_ENONFINITE;
