@@ -39,6 +39,7 @@ struct BJob {
     int dtype, ns;
     const subsurf4d_centre* seeds;
     double *I0, *ITH, *S0, *S1;   // interior FP64 scratch carved from the coefficient region
+    double *HR0, *HR1, *HJ0, *HJ1;  // colour-split rhs and iterate of the two heat solves (same region)
     double *R0, *R1;              // red values of the last iterate of each heat solve (same region)
 };
 

@@ -339,14 +339,89 @@ __global__ __launch_bounds__(kBlock) void kp_lhe_decide(PTable T)
     }
 }
 
-// SOR half-sweep of colour COLOR on the unfinished systems, with the
-// stopping-rule residual of its rows fused in (the iterate is that of the
-// red-black pass counter p = *T.pass).  The red sweep of pass p forms the red
-// rows of iterate p-1, rhs - A J before their update, and keeps iterate p-1's
-// red values in R; the black sweep of pass p forms the black rows of iterate p
-// right after their update.  One partial of r^2 per wave and
-// item: red items first, then black items.  A lane takes one cell of the swept
-// colour (flat per-colour numbering q = r*half + m, cell i = 2m + 2 - par).
+// The heat solves run on colour-split copies: colour c's cells at c*ncq + h,
+// h = row*half + m the flat per-colour numbering (cell i = 2m + 2 - par of the
+// interior row).  In the other colour's half, a cell's x-neighbours are
+// h - par and h + 1 - par, and its y-, z- and t-neighbours keep m in the
+// adjacent row, plane and frame, so every access of a sweep is a contiguous
+// run.  Slots past a row's last cell of a colour hold 0 and are never read.
+__device__ __forceinline__ uint32_t heat_q(const BJob& J, const Cell& cc)
+{
+    return ((((uint32_t)cc.l - 1) * (uint32_t)J.n3 + ((uint32_t)cc.k - 1)) * (uint32_t)J.n2 + ((uint32_t)cc.j - 1)) *
+               (uint32_t)J.n1 + (uint32_t)(2 * cc.m + 1 - cc.par);
+}
+
+template <int COLOR>
+__global__ __launch_bounds__(kBlock) void kp_heat_split(PTable T)
+{
+    for_runs(T.col_start, nullptr, T.n_jobs, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
+        const BJob J = T.jobs[jb];
+        const uint32_t ncq = (uint32_t)J.ncq;
+        for (uint32_t item = i0; item < i1; item += step) {
+            const uint32_t h = item * kItem + threadIdx.x;
+            if (h >= ncq) continue;
+            Cell cc;
+            double v0 = 0.0, v1 = 0.0;
+            if (bdecode(J, COLOR, h, cc)) {
+                const uint32_t q = heat_q(J, cc);
+                v0 = J.I0[q];
+                v1 = J.ITH[q];
+            }
+            const uint32_t o = COLOR * ncq + h;
+            J.HR0[o] = v0; J.HJ0[o] = v0;
+            J.HR1[o] = v1; J.HJ1[o] = v1;
+        }
+    });
+}
+
+// the split iterates back into the natural S0 / S1
+template <int COLOR>
+__global__ __launch_bounds__(kBlock) void kp_heat_merge(PTable T)
+{
+    for_runs(T.col_start, nullptr, T.n_jobs, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
+        const BJob J = T.jobs[jb];
+        const uint32_t ncq = (uint32_t)J.ncq;
+        for (uint32_t item = i0; item < i1; item += step) {
+            const uint32_t h = item * kItem + threadIdx.x;
+            Cell cc;
+            if (!bdecode(J, COLOR, h, cc)) continue;
+            const uint32_t q = heat_q(J, cc);
+            J.S0[q] = J.HJ0[COLOR * ncq + h];
+            J.S1[q] = J.HJ1[COLOR * ncq + h];
+        }
+    });
+}
+
+// Row of cell h of colour COLOR on the split copies: returns rhs + a sum_nbrs
+// (other colour, interior neighbours only) and sets *D = 1 + a n_P; the
+// neighbours are summed in the order -x, +x, -y, +y, -z, +z, -t, +t.
+template <int COLOR>
+__device__ __forceinline__ double lhe_row_split(const BJob& J, double a, const double* __restrict__ R,
+                                                const double* __restrict__ O, uint32_t h, const Cell& cc, double* D)
+{
+    const uint32_t sy = (uint32_t)J.half, sz = sy * (uint32_t)J.n2, st = sz * (uint32_t)J.n3;
+    const int i = 2 * cc.m + 2 - cc.par;
+    double s = R[h];
+    int cnt = 0;
+    if (i > 1) { s += a * O[h - cc.par]; ++cnt; }
+    if (i < J.n1) { s += a * O[h + 1 - cc.par]; ++cnt; }
+    if (cc.j > 1) { s += a * O[h - sy]; ++cnt; }
+    if (cc.j < J.n2) { s += a * O[h + sy]; ++cnt; }
+    if (cc.k > 1) { s += a * O[h - sz]; ++cnt; }
+    if (cc.k < J.n3) { s += a * O[h + sz]; ++cnt; }
+    if (cc.l > 1) { s += a * O[h - st]; ++cnt; }
+    if (cc.l < J.n4) { s += a * O[h + st]; ++cnt; }
+    *D = 1.0 + a * cnt;
+    return s;
+}
+
+// SOR half-sweep of colour COLOR on the split copies of the unfinished
+// systems, with the stopping-rule residual of its rows fused in (the iterate is
+// that of the red-black pass counter p = *T.pass).  The red sweep of pass p
+// forms the red rows of iterate p-1, rhs - A J before their update, and keeps
+// iterate p-1's red values in R0 / R1; the black sweep of pass p forms the
+// black rows of iterate p right after their update.  One partial of r^2 per
+// wave and item: red items first, then black items.
 template <int COLOR>
 __global__ __launch_bounds__(kBlock) void kp_lhe_sweep(PTable T)
 {
@@ -355,30 +430,32 @@ __global__ __launch_bounds__(kBlock) void kp_lhe_sweep(PTable T)
         const BJob J = T.jobs[jb];
         const bool run0 = !J.C->done, run1 = !J.C2->done;
         if (!run0 && !run1) return;
+        const uint32_t ncq = (uint32_t)J.ncq;
+        const uint32_t own = COLOR * ncq, oth = (1 - COLOR) * ncq;
         const uint32_t pbase = COLOR ? (uint32_t)J.nit : 0u;
         for (uint32_t item = i0; item < i1; item += step) {
             double r0 = 0.0, r1 = 0.0;
+            const uint32_t h = item * kItem + threadIdx.x;
             Cell cc;
-            if (bdecode(J, COLOR, item * kItem + threadIdx.x, cc)) {
-                const ICell c{2 * cc.m + 2 - cc.par, cc.j, cc.k, cc.l};
-                const uint32_t q = ((((uint32_t)c.l - 1) * (uint32_t)J.n3 + ((uint32_t)c.k - 1)) * (uint32_t)J.n2 +
-                                    ((uint32_t)c.j - 1)) * (uint32_t)J.n1 + ((uint32_t)c.i - 1);
+            if (bdecode(J, COLOR, h, cc)) {
                 double D;
                 if (run0) {
-                    const double s = lhe_row(J, a, J.I0, J.S0, q, c, &D);
-                    const double uold = J.S0[q], unew = om * (s / D) + om1 * uold;
-                    J.S0[q] = unew;
+                    const double s = lhe_row_split<COLOR>(J, a, J.HR0 + own, J.HJ0 + oth, h, cc, &D);
+                    double* W = J.HJ0 + own;
+                    const double uold = W[h], unew = om * (s / D) + om1 * uold;
+                    W[h] = unew;
                     const double r = s - D * (COLOR == 0 ? uold : unew);
                     r0 = r * r;
-                    if (COLOR == 0) J.R0[q] = uold;
+                    if (COLOR == 0) J.R0[h] = uold;
                 }
                 if (run1) {
-                    const double s = lhe_row(J, a, J.ITH, J.S1, q, c, &D);
-                    const double uold = J.S1[q], unew = om * (s / D) + om1 * uold;
-                    J.S1[q] = unew;
+                    const double s = lhe_row_split<COLOR>(J, a, J.HR1 + own, J.HJ1 + oth, h, cc, &D);
+                    double* W = J.HJ1 + own;
+                    const double uold = W[h], unew = om * (s / D) + om1 * uold;
+                    W[h] = unew;
                     const double r = s - D * (COLOR == 0 ? uold : unew);
                     r1 = r * r;
-                    if (COLOR == 0) J.R1[q] = uold;
+                    if (COLOR == 0) J.R1[h] = uold;
                 }
             }
             const double s0 = wave_sum(r0), s1 = wave_sum(r1);
@@ -420,20 +497,20 @@ __global__ __launch_bounds__(kBlock) void kp_lhe_decide_lag(PTable T)
 }
 
 // A system decided on iterate k >= 1 at pass k+1, whose red sweep had already
-// moved its red cells on: put iterate k's red values back.
+// moved its red cells on: put iterate k's red values back (red half of the
+// split copy; the other slots are never read).
 __global__ __launch_bounds__(kBlock) void kp_lhe_restore(PTable T)
 {
     for_runs(T.col_start, nullptr, T.n_jobs, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
         const BJob J = T.jobs[jb];
         const bool b0 = J.C->iterations >= 1, b1 = J.C2->iterations >= 1;
         if (!b0 && !b1) return;
+        const uint32_t ncq = (uint32_t)J.ncq;
         for (uint32_t item = i0; item < i1; item += step) {
-            Cell cc;
-            if (!bdecode(J, 0, item * kItem + threadIdx.x, cc)) continue;
-            const uint32_t q = ((((uint32_t)cc.l - 1) * (uint32_t)J.n3 + ((uint32_t)cc.k - 1)) * (uint32_t)J.n2 +
-                                ((uint32_t)cc.j - 1)) * (uint32_t)J.n1 + (uint32_t)(2 * cc.m + 1 - cc.par);
-            if (b0) J.S0[q] = J.R0[q];
-            if (b1) J.S1[q] = J.R1[q];
+            const uint32_t h = item * kItem + threadIdx.x;
+            if (h >= ncq) continue;
+            if (b0) J.HJ0[h] = J.R0[h];
+            if (b1) J.HJ1[h] = J.R1[h];
         }
     });
 }
@@ -584,9 +661,10 @@ int run_batch_prepare_on(const subsurf4d_batch_prepare_job* jobs, int n_jobs, co
         const subsurf4d_batch_prepare_job& pj = jobs[q];
         BJob J;
         if (int rc = bind_batch_job(pj.grid.n, pj.n_centres, pj.workspace, pj.workspace_bytes, &J)) return rc;
-        // scratch: six interior FP64 fields in the coefficient region
+        // scratch in the coefficient region: four interior FP64 fields, the
+        // split rhs and iterate of both heat solves and their kept red values
         const size_t coef_bytes = sizeof(double) * 2 * (size_t)J.ntq * kTileVals;
-        if (coef_bytes < 6 * sizeof(double) * (size_t)J.nint) {
+        if (coef_bytes < sizeof(double) * (4 * (size_t)J.nint + 10 * (size_t)J.ncq)) {
             set_error("internal: batched preparation scratch does not fit");
             return SUBSURF4D_EDEVICE;
         }
@@ -594,8 +672,12 @@ int run_batch_prepare_on(const subsurf4d_batch_prepare_job* jobs, int n_jobs, co
         J.ITH = J.I0 + J.nint;
         J.S0 = J.ITH + J.nint;
         J.S1 = J.S0 + J.nint;
-        J.R0 = J.S1 + J.nint;
-        J.R1 = J.R0 + J.nint;
+        J.HR0 = J.S1 + J.nint;
+        J.HR1 = J.HR0 + 2 * J.ncq;
+        J.HJ0 = J.HR1 + 2 * J.ncq;
+        J.HJ1 = J.HJ0 + 2 * J.ncq;
+        J.R0 = J.HJ1 + 2 * J.ncq;
+        J.R1 = J.R0 + J.ncq;
         J.inv_h = 1.0 / pj.grid.h;
         J.G = pj.G;
         J.u = pj.u;
@@ -691,6 +773,8 @@ int run_batch_prepare_on(const subsurf4d_batch_prepare_job* jobs, int n_jobs, co
             kp_lhe_bnorm<<<g_job, kBlock, 0, s>>>(T);
             kp_lhe_residual<<<g_cell, kBlock, 0, s>>>(T);
             kp_lhe_decide<<<g_job, kBlock, 0, s>>>(T);
+            kp_heat_split<0><<<g_cell, kBlock, 0, s>>>(T);
+            kp_heat_split<1><<<g_cell, kBlock, 0, s>>>(T);
             e = hipGetLastError();
             int active = 2 * n_jobs, k = 0, chunk = 4;
             while (e == hipSuccess) {
@@ -710,6 +794,8 @@ int run_batch_prepare_on(const subsurf4d_batch_prepare_job* jobs, int n_jobs, co
             }
             if (e == hipSuccess && rc == 0) {
                 kp_lhe_restore<<<g_cell, kBlock, 0, s>>>(T);
+                kp_heat_merge<0><<<g_cell, kBlock, 0, s>>>(T);
+                kp_heat_merge<1><<<g_cell, kBlock, 0, s>>>(T);
                 kp_gather<<<(n_jobs + 255) / 256, 256, 0, s>>>(T);
                 e = hipMemcpyAsync(hout.data(), T.out, sizeof(int4) * n_jobs, hipMemcpyDeviceToHost, s);
                 if (e == hipSuccess) e = hipStreamSynchronize(s);
