@@ -2,6 +2,7 @@
 // implicit zero-Neumann presmoothing, face edge detector G, initial function,
 // local rescaling (Sec. 3.1 and Sec. 3.2.2 of the paper).
 #include <climits>
+#include <cstdlib>
 #include <cmath>
 #include <type_traits>
 
@@ -573,11 +574,21 @@ int lhe_solve_t(const WsPlan& P, double a, double omega, double tol, int max_ite
     return 0;
 }
 
+// Grids below 2^31 cells take the 32-bit index decode.  SUBSURF4D_WIDE_INDEX=1
+// forces the 64-bit form (read at every call), so that tests can check on
+// small grids that both forms give the same bits.
+bool wide_index_forced()
+{
+    const char* e = getenv("SUBSURF4D_WIDE_INDEX");
+    return e && e[0] == '1';
+}
+
 int lhe_solve(const WsPlan& P, double a, double omega, double tol, int max_iter, const double* rhs,
               double* J, void* ws, hipStream_t s, int* status)
 {
     const Layout& L = P.L;
-    const bool narrow = L.nrow_int * L.half < ((int64_t)1 << 31) && L.nint < ((int64_t)1 << 31);
+    const bool narrow = L.nrow_int * L.half < ((int64_t)1 << 31) && L.nint < ((int64_t)1 << 31) &&
+                        !wide_index_forced();
     return narrow ? lhe_solve_t<true>(P, a, omega, tol, max_iter, rhs, J, ws, s, status)
                   : lhe_solve_t<false>(P, a, omega, tol, max_iter, rhs, J, ws, s, status);
 }
@@ -632,7 +643,7 @@ int run_prepare(const WsPlan& P, double h, const void* image, int dtype, const s
         double* t1 = src1; src1 = dst1; dst1 = t1;
     }
     const uint64_t mp1 = fdiv_magic((uint32_t)L.p1), mp2 = fdiv_magic((uint32_t)L.p2), mp3 = fdiv_magic((uint32_t)L.p3);
-    if (L.npad < ((int64_t)1 << 31))
+    if (L.npad < ((int64_t)1 << 31) && !wide_index_forced())
         k_face_g<true><<<grid_for(L.npad), kBlock, 0, s>>>(L, mp1, mp2, mp3, 1.0 / h, pp.K, pp.delta, pp.vartheta,
                                                            src0, src1, G);
     else

@@ -184,3 +184,19 @@ def test_batched_prepare_heat_solve_cut_by_max_iter(cap):
         assert np.abs(H(j.G) - H(one.G)).max() <= 1e-13
         # the limit did cut the solve short
         assert np.abs(H(j.G) - H(f.G)).max() > 1e-9
+
+
+def test_prepare_wide_index_form_same_bits(monkeypatch):
+    """The single-job preparation decodes cell indices with 32-bit multiplies
+    on grids below 2^31 cells and with 64-bit divisions above; forcing the
+    64-bit form on small grids (odd and even row lengths) gives the same G."""
+    for n in [(33, 25, 28, 5), (24, 30, 26, 3)]:
+        im = synth.window_job(n, 9100, 109100)
+        a = B.Job(n, im.image, im.centres, im.seeds, precision=B.FP64)
+        assert a.prepare(PP) == 0
+        monkeypatch.setenv("SUBSURF4D_WIDE_INDEX", "1")
+        b = B.Job(n, im.image, im.centres, im.seeds, precision=B.FP64)
+        assert b.prepare(PP) == 0
+        monkeypatch.delenv("SUBSURF4D_WIDE_INDEX")
+        np.testing.assert_array_equal(H(a.G), H(b.G))
+        np.testing.assert_array_equal(H(a.owner), H(b.owner))
