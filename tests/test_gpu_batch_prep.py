@@ -200,3 +200,21 @@ def test_prepare_wide_index_form_same_bits(monkeypatch):
         monkeypatch.delenv("SUBSURF4D_WIDE_INDEX")
         np.testing.assert_array_equal(H(a.G), H(b.G))
         np.testing.assert_array_equal(H(a.owner), H(b.owner))
+
+
+def test_prepare_degenerate_shapes_single_and_batched():
+    """Rows of one or two cells (one colour empty in a row, or a single cell
+    of each), single planes and frames, a single cell: the colour-split heat
+    solves and the face G of both forms against the oracle."""
+    sizes = [(1, 5, 4, 3), (2, 3, 1, 2), (5, 1, 1, 4), (3, 2, 2, 1), (1, 1, 1, 1), (2, 2, 2, 2), (7, 1, 3, 1)]
+    ims = [synth.window_job(n, 9300 + q, 109300 + q) for q, n in enumerate(sizes)]
+    rc, st, jobs = batched(ims)
+    assert rc == 0 and st == [0] * len(ims)
+    for im, j in zip(ims, jobs):
+        prep, _ = oracle_prep(im)
+        np.testing.assert_array_equal(H(j.owner), prep["owner"])
+        assert np.abs(H(j.G) - prep["G"]).max() <= 1e-12, im.n
+        one = B.Job(im.n, im.image, im.centres, im.seeds, precision=B.FP64)
+        assert one.prepare(PP) == 0
+        assert np.abs(H(one.G) - prep["G"]).max() <= 1e-12, im.n
+        assert np.abs(H(one.G) - H(j.G)).max() <= 1e-13, im.n
