@@ -297,6 +297,12 @@ __global__ __launch_bounds__(kBlock) void k_heat_merge(Layout L, HeatDiv M, cons
 // black rows in part_k.  The last block of the red sweep of pass p >= 2 judges
 // iterate p-1; a system stopped there has its red cells put back by
 // k_lhe_restore.
+//
+// A lane owns slot g = ((k-1)*N2 + (j-1))*half + m of every frame and marches
+// through the frames (h = g + (l-1)*ncq2): the other colour's values at the
+// lane's own slot in frames l-1, l and l+1 stay in registers, so each frame
+// of the other colour is read once instead of three times.  The neighbours are
+// summed in the order -x, +x, -y, +y, -z, +z, -t, +t.
 template <int COLOR, bool NARROW>
 __global__ __launch_bounds__(kBlock) void k_lhe_sweep(Layout L, HeatDiv M, double a, double omega,
                                                       const double* __restrict__ rhs, double* J,
@@ -306,35 +312,57 @@ __global__ __launch_bounds__(kBlock) void k_lhe_sweep(Layout L, HeatDiv M, doubl
     __shared__ double lds[4];
     __shared__ int flag;
     if (C->done) return;
-    // one lane per cell of colour COLOR, so no lane idles on the other colour
     const int64_t ncq = L.nrow_int * L.half;
-    const int64_t sy = L.half, sz = (int64_t)L.half * L.n2, st = sz * L.n3;
+    const int64_t ncq2 = (int64_t)L.half * L.n2 * L.n3;   // slots of one frame
+    const int64_t sy = L.half, sz = (int64_t)L.half * L.n2;
     const double* __restrict__ R = rhs + COLOR * ncq;
     const double* __restrict__ O = J + (1 - COLOR) * ncq;   // the other colour: read only
     double* __restrict__ W = J + COLOR * ncq;               // this colour: updated
     double acc = 0.0;
-    for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < ncq; h += (int64_t)gridDim.x * blockDim.x) {
-        int64_t q;
-        int i, j, k, l;
-        if (!heat_cell<COLOR, NARROW>(L, M, h, q, i, j, k, l)) continue;
-        const int par = (COLOR + j + k + l) & 1;
-        double s = R[h];
-        int cnt = 0;
-        if (i > 1) { s += a * O[h - par]; ++cnt; }
-        if (i < L.n1) { s += a * O[h + 1 - par]; ++cnt; }
-        if (j > 1) { s += a * O[h - sy]; ++cnt; }
-        if (j < L.n2) { s += a * O[h + sy]; ++cnt; }
-        if (k > 1) { s += a * O[h - sz]; ++cnt; }
-        if (k < L.n3) { s += a * O[h + sz]; ++cnt; }
-        if (l > 1) { s += a * O[h - st]; ++cnt; }
-        if (l < L.n4) { s += a * O[h + st]; ++cnt; }
-        const double D = 1.0 + a * cnt;
-        const double uold = W[h];
-        const double unew = omega * (s / D) + (1.0 - omega) * uold;
-        W[h] = unew;
-        const double r = s - D * (COLOR == 0 ? uold : unew);
-        acc += r * r;
-        if (COLOR == 0) saved[h] = uold;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ncq2; g += (int64_t)gridDim.x * blockDim.x) {
+        int m, j, k;
+        if (NARROW) {
+            const uint32_t gg = (uint32_t)g;
+            const uint32_t r = fdiv(gg, M.half);
+            m = (int)(gg - r * (uint32_t)L.half);
+            const uint32_t r2 = fdiv(r, M.n2);
+            j = (int)(r - r2 * (uint32_t)L.n2) + 1;
+            k = (int)r2 + 1;
+        } else {
+            const int64_t r = g / L.half;
+            m = (int)(g - r * L.half);
+            j = (int)(r % L.n2) + 1;
+            k = (int)(r / L.n2) + 1;
+        }
+        double oprev = 0.0, ocur = O[g];
+        for (int l = 1; l <= L.n4; ++l) {
+            const int64_t h = g + (int64_t)(l - 1) * ncq2;
+            const double onext = l < L.n4 ? O[h + ncq2] : 0.0;
+            const int par = (COLOR + j + k + l) & 1;
+            if (m < (par ? (L.n1 + 1) >> 1 : L.n1 >> 1)) {
+                const int i = 2 * m + 2 - par;
+                double s = R[h];
+                int cnt = 0;
+                // x-neighbours h - par and h + 1 - par: one of them is h itself
+                if (i > 1) { s += a * (par ? O[h - 1] : ocur); ++cnt; }
+                if (i < L.n1) { s += a * (par ? ocur : O[h + 1]); ++cnt; }
+                if (j > 1) { s += a * O[h - sy]; ++cnt; }
+                if (j < L.n2) { s += a * O[h + sy]; ++cnt; }
+                if (k > 1) { s += a * O[h - sz]; ++cnt; }
+                if (k < L.n3) { s += a * O[h + sz]; ++cnt; }
+                if (l > 1) { s += a * oprev; ++cnt; }
+                if (l < L.n4) { s += a * onext; ++cnt; }
+                const double D = 1.0 + a * cnt;
+                const double uold = W[h];
+                const double unew = omega * (s / D) + (1.0 - omega) * uold;
+                W[h] = unew;
+                const double r = s - D * (COLOR == 0 ? uold : unew);
+                acc += r * r;
+                if (COLOR == 0) saved[h] = uold;
+            }
+            oprev = ocur;
+            ocur = onext;
+        }
     }
     const double bs = block_sum(acc, lds);
     if (threadIdx.x == 0) (COLOR == 0 ? part_r : part_k)[blockIdx.x] = bs;
@@ -533,6 +561,7 @@ int lhe_solve_t(const WsPlan& P, double a, double omega, double tol, int max_ite
     double* HR = ws_ptr<double>(ws, P.HR);       // split right-hand side
     double* HJ = ws_ptr<double>(ws, P.HJ);       // split iterate
     const int gs = grid_for(L.nrow_int * L.half);
+    const int gm = grid_for((int64_t)L.half * L.n2 * L.n3);   // marching sweeps: one lane per slot of a frame
     // the residual's per-block partials fit the workspace's partial arrays
     // (at least kGridCap entries), so it takes a full grid as well
     const int gr = grid_for(L.nint);
@@ -556,8 +585,8 @@ int lhe_solve_t(const WsPlan& P, double a, double omega, double tol, int max_ite
             return SUBSURF4D_EDEVICE;
         }
         for (int c = 0; c < chunk && k <= max_iter + 1; ++c, ++k) {
-            k_lhe_sweep<0, NARROW><<<gs, kBlock, 0, s>>>(L, M, a, omega, HR, HJ, saved, k, pa, pb, C);
-            k_lhe_sweep<1, NARROW><<<gs, kBlock, 0, s>>>(L, M, a, omega, HR, HJ, saved, k, pa, pb, C);
+            k_lhe_sweep<0, NARROW><<<gm, kBlock, 0, s>>>(L, M, a, omega, HR, HJ, saved, k, pa, pb, C);
+            k_lhe_sweep<1, NARROW><<<gm, kBlock, 0, s>>>(L, M, a, omega, HR, HJ, saved, k, pa, pb, C);
         }
         SS4_LAUNCHED("lhe sweeps");
         if (chunk < 32) chunk *= 2;
