@@ -40,6 +40,22 @@ def test_host_queries():
     assert B.lib().subsurf4d_status_string(-3) == b"workspace too small"
 
 
+def test_prepare_workspace_fits_in_the_step_workspace():
+    """The header promises subsurf4d_prepare_workspace_bytes <=
+    subsurf4d_workspace_bytes, so one workspace serves both calls; checked over
+    odd, even and unit extents, with and without centres, both precisions."""
+    import itertools
+
+    from paper_2111_11866_amd import binding as B
+
+    for n in itertools.product([1, 2, 7, 24, 65], [1, 2, 33], [1, 3, 16], [1, 2, 9]):
+        for nc in (0, 5):
+            pw = B.prepare_workspace_bytes(n, nc)
+            assert pw > 0
+            for prec in (B.FP64, B.MIXED):
+                assert pw <= B.workspace_bytes(n, nc, prec), (n, nc, prec)
+
+
 def test_batch_queries():
     from paper_2111_11866_amd import binding as B
 
