@@ -84,7 +84,7 @@ typedef struct {
     double ball_r;        /* ball radius r (voxels) of the local thresholding */
     double smooth_tau;    /* presmoothing: implicit heat-step size (finite, >= 0) */
     int32_t smooth_steps; /* number of implicit heat steps (>= 0) */
-    int32_t smooth_max_iter; /* SOR iteration cap of each heat step */
+    int32_t smooth_max_iter; /* SOR iteration cap of each heat step, in [1, 2^30] */
     double smooth_omega;  /* SOR relaxation of the heat steps, in (0,2); <= 0: Young's optimum
                              2/(1+sqrt(1-rho^2)), rho = 8a/(1+8a), a = smooth_tau/h^2 */
     double smooth_tol;    /* relative L2 residual tolerance of the heat steps */
@@ -98,14 +98,14 @@ typedef struct {
     double omega;         /* SOR relaxation, in (0,2); MIXED: relaxation of the inner FP32
                              sweeps only (the FP64 residual and refine_tol decide the result) */
     double tol;           /* stop at ||b - A u||_2 <= tol ||b||_2 (relative L2) */
-    int32_t max_iter;     /* iteration cap (>= 1) */
+    int32_t max_iter;     /* iteration cap, in [1, 2^30] */
     int32_t check_every;  /* test the stopping rule every this many iterations (0 means 1) */
     int32_t rescale;      /* 1: local rescaling after the solve (needs owner/centres) */
     int32_t precision;    /* SUBSURF4D_FP64 or SUBSURF4D_MIXED */
     double ball_r;        /* ball radius of the local rescaling */
     double refine_tol;    /* MIXED: FP64 relative residual target of refinement */
-    int32_t inner_sweeps; /* MIXED: FP32 red-black iterations per refinement pass */
-    int32_t fixed_iters;  /* > 0: run exactly this many iterations (tol ignored; FP64 only) */
+    int32_t inner_sweeps; /* MIXED: FP32 red-black iterations per refinement pass, in [1, 1024] */
+    int32_t fixed_iters;  /* > 0: run exactly this many iterations, at most 2^30 (tol ignored; FP64 only) */
     int32_t iter_hint;    /* expected iteration count (0 = unknown); only sizes launch chunks */
     int32_t flags;        /* SUBSURF4D_FLAG_* bits */
 } subsurf4d_step_params;

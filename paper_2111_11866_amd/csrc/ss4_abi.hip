@@ -149,6 +149,8 @@ int check_ws(const WsPlan& P, void* ws, size_t bytes, size_t need = 0)
     return 0;
 }
 
+constexpr int32_t kMaxIterCap = 1 << 30;
+
 int check_step_params(const subsurf4d_step_params* p)
 {
     if (!p) return fail(SUBSURF4D_EINVAL, "params is NULL");
@@ -156,14 +158,18 @@ int check_step_params(const subsurf4d_step_params* p)
     if (!(p->tau >= 0.0) || !std::isfinite(p->tau)) return fail(SUBSURF4D_EINVAL, "tau must be >= 0");
     if (!(p->omega > 0.0 && p->omega < 2.0)) return fail(SUBSURF4D_EINVAL, "omega must be in (0,2)");
     if (!(p->tol >= 0.0)) return fail(SUBSURF4D_EINVAL, "tol must be >= 0");
-    if (p->fixed_iters <= 0 && p->max_iter < 1) return fail(SUBSURF4D_EINVAL, "max_iter must be >= 1");
+    // iteration counts stay far from INT_MAX, so pass counters (max_iter + 1) cannot overflow
+    if (p->fixed_iters <= 0 && (p->max_iter < 1 || p->max_iter > kMaxIterCap))
+        return fail(SUBSURF4D_EINVAL, "max_iter must be in [1, 2^30]");
+    if (p->fixed_iters > kMaxIterCap) return fail(SUBSURF4D_EINVAL, "fixed_iters must be <= 2^30");
     if (p->check_every < 0) return fail(SUBSURF4D_EINVAL, "check_every must be >= 0");
     if (p->precision != SUBSURF4D_FP64 && p->precision != SUBSURF4D_MIXED)
         return fail(SUBSURF4D_EINVAL, "unknown precision");
     if (p->rescale && !(p->ball_r >= 0.0 && p->ball_r <= 1e6)) return fail(SUBSURF4D_EINVAL, "ball_r out of range");
     if (p->precision == SUBSURF4D_MIXED) {
         if (!(p->refine_tol > 0.0)) return fail(SUBSURF4D_EINVAL, "refine_tol must be > 0");
-        if (p->inner_sweeps < 1) return fail(SUBSURF4D_EINVAL, "inner_sweeps must be >= 1");
+        if (p->inner_sweeps < 1 || p->inner_sweeps > 1024)
+            return fail(SUBSURF4D_EINVAL, "inner_sweeps must be in [1, 1024]");
     }
     const int known = SUBSURF4D_FLAG_NO_GRAPH | SUBSURF4D_FLAG_SWEEP_FLAT | SUBSURF4D_FLAG_SWEEP_MARCH;
     if (p->flags & ~known) return fail(SUBSURF4D_EINVAL, "unknown flags");
@@ -224,7 +230,7 @@ int check_prepare_params(const subsurf4d_prepare_params* params)
     if (!(p.smooth_tau >= 0.0) || !std::isfinite(p.smooth_tau) || p.smooth_steps < 0)
         return fail(SUBSURF4D_EINVAL, "bad smoothing parameters");
     if (p.smooth_steps > 0 && (!(p.smooth_omega < 2.0) || p.smooth_max_iter < 1 ||
-                               !(p.smooth_tol >= 0.0)))
+                               p.smooth_max_iter > kMaxIterCap || !(p.smooth_tol >= 0.0)))
         return fail(SUBSURF4D_EINVAL, "bad smoothing solver parameters");
     if (!std::isfinite(p.image_scale)) return fail(SUBSURF4D_EINVAL, "image_scale must be finite");
     return 0;

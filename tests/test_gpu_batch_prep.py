@@ -140,7 +140,7 @@ def test_batched_prepare_bad_arguments(imgs):
     with pytest.raises(B.Subsurf4dError):
         B.prepare_batched(jobs, PP, 0.0, 0.0, BALL_R, table)
     for bad in (dict(delta=float("nan")), dict(vartheta=-1.0), dict(delta=float("inf")),
-                dict(smooth_tau=float("inf"))):
+                dict(smooth_tau=float("inf")), dict(smooth_max_iter=2 ** 31 - 1)):
         with pytest.raises(B.Subsurf4dError):
             B.prepare_batched(jobs, replace(PP, **bad), 1.0, 0.0, BALL_R, table)
 

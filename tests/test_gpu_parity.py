@@ -417,6 +417,17 @@ def test_bad_arguments_rejected():
     with pytest.raises(B.Subsurf4dError) as e:
         B.solve(n, 1.0, T(coef), T(b), T(w), B.StepParams(omega=2.0, rescale=False), B.alloc_workspace(n))
     assert e.value.status == B.EINVAL
+    # iteration caps far from INT_MAX (pass counters run to max_iter + 1)
+    for bad in (dict(max_iter=(1 << 30) + 1), dict(max_iter=2 ** 31 - 1), dict(fixed_iters=(1 << 30) + 1),
+                dict(precision=B.MIXED, inner_sweeps=1025)):
+        with pytest.raises(B.Subsurf4dError) as e:
+            B.solve(n, 1.0, T(coef), T(b), T(w), B.StepParams(rescale=False, **bad), B.alloc_workspace(n))
+        assert e.value.status == B.EINVAL, bad
+    im = synth.window_job(n, 5, 6)
+    job = B.Job(n, im.image, im.centres, im.seeds, precision=B.FP64)
+    with pytest.raises(B.Subsurf4dError) as e:
+        job.prepare(B.PrepareParams(image_scale=1.0 / 255.0, smooth_max_iter=2 ** 31 - 1))
+    assert e.value.status == B.EINVAL
 
 
 def test_deterministic_repeat(cfg1):
