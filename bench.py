@@ -20,8 +20,8 @@ when it was taken on the current kernel sources.
 
 The same JSON line also carries:
 * mixed: the same job with the mixed-precision solve (FP32 sweeps on BF16
-  coefficients in FP64 refinement; 10 sweeps per pass at omega 1.5) at the
-  FP64 stopping rule and at 1e-10;
+  coefficients in FP64 refinement; 20 sweeps per pass at the FP64 omega) at
+  the FP64 stopping rule and at 1e-10;
 * cpu_baseline: the oracle's red-black SOR on the host cores, on a bounded
   crop of the same volume;
 * batched_windows: 2048 uneven windows (x,y,z in 24..64, t in 3..9) of 20
@@ -278,9 +278,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mixed-steps", type=int, default=-1,
                     help="also time this many steps with the mixed-precision solve (-1: same as --steps)")
-    ap.add_argument("--inner", type=int, default=10, help="FP32 sweeps per refinement pass (mixed)")
-    ap.add_argument("--inner-omega", type=float, default=1.5,
-                    help="relaxation of the FP32 sweeps of the correction equation (mixed)")
+    ap.add_argument("--inner", type=int, default=20, help="FP32 sweeps per refinement pass (mixed)")
+    ap.add_argument("--inner-omega", type=float, default=0.0,
+                    help="relaxation of the FP32 sweeps of the correction equation (mixed); "
+                         "0: the FP64 solve's omega")
     ap.add_argument("--windows", type=int, default=2048, help="batched workload size (0: skip)")
     ap.add_argument("--window-steps", type=int, default=20)
     ap.add_argument("--plain-sample", type=int, default=24)
@@ -313,6 +314,8 @@ def main():
     log(f"[bench] generated {n} with {len(img.centres)} centres in {time.perf_counter() - t0:.1f}s")
     pp = B.PrepareParams(image_scale=1.0 / 255.0)
     sp = B.StepParams(omega=1.8)
+    if args.inner_omega <= 0.0:
+        args.inner_omega = sp.omega
 
     job = B.Job(n, img.image, img.centres, img.seeds, precision=B.MIXED)
     t0 = time.perf_counter()

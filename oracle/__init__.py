@@ -306,39 +306,52 @@ def interior(a_padded):
 # ---------------------------------------------------------------- EOC test
 
 
-def eoc_run(N, steps, T=0.0625, L=1.25, omega=1.5, tol=1e-11):
+def eoc_run(N, steps, T=0.0625, L=1.25, omega=1.5, tol=1e-11, grid="cell", eps=None, lagged_dirichlet=False):
     """Sec. 3.4: level-set mean-curvature flow with the exact solution
-    u = (x1^2+x2^2+x3^2+x4^2 - 1)/6 + t on [-L, L]^4, G = 1, eps = h^2,
-    tau = T/steps, Dirichlet data from the exact solution.
+    u = (x1^2+x2^2+x3^2+x4^2 - 1)/6 + t on [-L, L]^4, G = 1, tau = T/steps,
+    Dirichlet data from the exact solution, no rescaling.  Returns the
+    L2(0,T;L2) error sqrt(sum_n tau * sum_P h^4 (u^n_P - u(x_P, t_n))^2) and
+    the SOR iteration counts.
 
-    Reading: cell-centred grid x_i = -L + (i - 1/2) h (ghost centres one h
-    outside); the ghosts of u^{n-1} (used for the boundary-face gradients)
-    hold the exact solution at t_{n-1}, the Dirichlet data of the new level
-    the exact solution at t_n; no rescaling.  Returns the L2(0,T;L2) error
-    sqrt(sum_n tau * sum_P h^4 (u^n_P - u(x_P, t_n))^2).
+    The paper states the domain, N, the step counts, eps = h^2 and the norm,
+    not where the unknowns sit or when the boundary data are taken.  Readings:
+    grid="cell" (default): N cells of width h = 2L/N, centres
+    x_i = -L + (i - 1/2) h, ghost centres one h outside; grid="node": nodes
+    x_i = -L + i h, i = 0..N, with the N-1 interior nodes unknown and the
+    nodes on the boundary holding the data.  The ghosts of u^{n-1} (they feed
+    the boundary-face gradients) hold the exact solution at t_{n-1}; the
+    Dirichlet data of the new level are the exact solution at t_n, or at
+    t_{n-1} with lagged_dirichlet=True.  eps defaults to h^2.
     """
     h = 2 * L / N
-    n = (N, N, N, N)
-    x = -L + (np.arange(N + 2) - 0.5) * h
+    if grid == "cell":
+        x = -L + (np.arange(N + 2) - 0.5) * h
+        n = (N, N, N, N)
+    elif grid == "node":
+        x = -L + np.arange(N + 1) * h
+        n = (N - 1,) * 4
+    else:
+        raise ValueError(grid)
+    eps = h * h if eps is None else float(eps)
     X4, X3, X2, X1 = np.meshgrid(x, x, x, x, indexing="ij")
     r2 = X1 ** 2 + X2 ** 2 + X3 ** 2 + X4 ** 2
     exact = lambda t: (r2 - 1.0) / 6.0 + t  # noqa: E731
     tau = T / steps
     G = np.ones((4,) + padded_shape(n))
     w = exact(0.0)
+    inner = (slice(1, -1),) * 4
     err2 = 0.0
     its = []
     for s in range(1, steps + 1):
-        ub = exact(s * tau)
-        coef, b = assemble(n, G, w, h, h * h, tau, ub=ub)
-        u0 = w.copy()
-        u0[0, :, :, :] = ub[0]; u0[-1] = ub[-1]
-        u0[:, 0] = ub[:, 0]; u0[:, -1] = ub[:, -1]
-        u0[:, :, 0] = ub[:, :, 0]; u0[:, :, -1] = ub[:, :, -1]
-        u0[..., 0] = ub[..., 0]; u0[..., -1] = ub[..., -1]
+        ub = exact((s - 1) * tau if lagged_dirichlet else s * tau)
+        coef, b = assemble(n, G, w, h, eps, tau, ub=ub)
+        u0 = ub.copy()
+        u0[inner] = w[inner]
         u, it, rr, st = sor(n, coef, b, u0, omega, tol, 100000, RB)
         its.append(it)
-        e = interior(u) - interior(ub)
+        ex = exact(s * tau)
+        e = interior(u) - interior(ex)
         err2 += tau * (h ** 4) * float(np.sum(e * e))
-        w = u
+        w = ex.copy()                      # next level's gradient ghosts: exact solution at t_s
+        w[inner] = u[inner]
     return float(np.sqrt(err2)), its

@@ -93,7 +93,7 @@ static void ball_box(const int *n, const oracle_centre *c, double r, long lo[3],
  * The paper defines thresholding and rescaling per ball (Sec. 3.1 and the
  * local rescaling remark); overlapping balls are not discussed there, and the
  * nearest-centre owner is this implementation's reading.
- * Pinned by brute force on small inputs (tests/test_oracle_balls.py).
+ * Pinned by brute force on small inputs (tests/test_oracle_pins.py: owner map and threshold tests).
  */
 void oracle_owner_map(const int *n, const oracle_centre *cs, int nc, double r, int32_t *owner)
 {
@@ -195,7 +195,7 @@ static double norm2_interior(const int *n, const double *b)
  * first and after every iteration).  Interior arrays.  Returns iterations used,
  * or -1 if max_iter was reached.
  * Pinned by the Neumann cosine eigenmode, mass conservation and constants
- * (tests/test_oracle_lhe.py).
+ * (tests/test_oracle_pins.py: LHE eigenmode, mass and DMP tests).
  */
 static double lhe_row(const int *n, const double *J, const double *rhs, double a, long i, long j,
                       long k, long l, double *diag)
@@ -277,7 +277,7 @@ int oracle_lhe_step(const int *n, double h, double tau_s, double omega, double t
  * The "-e_d" face of P is the "+e_d" face of P-e_d (the paper's formulas with
  * p=-1 give the same vector up to the sign of the normal component, so the
  * same norm).  `get` reads v at a (possibly clamped) index.
- * Pinned: exact for every quadratic polynomial (tests/test_oracle_gradient.py).
+ * Pinned: exact for every quadratic polynomial (tests/test_oracle_pins.py: face-gradient quadratic test).
  */
 typedef double (*getter)(const void *ctx, long i, long j, long k, long l);
 

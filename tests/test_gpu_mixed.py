@@ -93,3 +93,30 @@ def test_mixed_not_converged():
     r = B.step(n, 1.0, G, None, 0, None, u, B.StepParams(precision=B.MIXED, rescale=False, refine_tol=1e-15,
                                                         inner_sweeps=2, max_iter=4), B.alloc_workspace(n, 0, B.MIXED))
     assert r["status"] == B.NOT_CONVERGED and r["outer"] == 2
+
+
+def test_mixed_passes_track_fp64_iterations(cfg1):
+    """Refinement with m inner red-black sweeps from a zero correction is, in
+    exact arithmetic, m steps of the same stationary SOR iteration, so a mixed
+    step needs about as many inner sweeps as FP64 SOR needs iterations for the
+    same tolerance and relaxation: passes * m <= K_fp64 + 2m on every step of
+    the config-1 trajectory (the BF16 coefficients do not slow the refinement
+    down as the system sharpens)."""
+    img, prep, w = cfg1
+    n = img.n
+    cen, nc = B.centres_tensor(img.centres)
+    owner, G = T(prep["owner"]), T(prep["G"])
+    ws = B.alloc_workspace(n, nc, B.MIXED)
+    m = 8
+    rows = []
+    for s in range(20):
+        u = T(w)
+        r64 = B.step(n, 1.0, G, cen, nc, owner, u, B.StepParams(tol=1e-10, rescale=False), ws)
+        u = T(w)
+        rmx = B.step(n, 1.0, G, cen, nc, owner, u, B.StepParams(precision=B.MIXED, refine_tol=1e-10,
+                                                                 inner_sweeps=m, rescale=False), ws)
+        assert r64["status"] == 0 and rmx["status"] == 0
+        rows.append((s, r64["iterations"], rmx["outer"]))
+        assert rmx["outer"] * m <= r64["iterations"] + 2 * m, rows
+        w = orc.step(n, prep["G"], w, img.centres, prep["owner"], orc.StepParams(), orc.RB)["u_resc"]
+    print("step, FP64 iterations to 1e-10, mixed passes:", rows)

@@ -56,3 +56,27 @@ def test_window_forms_within_1e6_of_converged():
         for q, (a, r) in enumerate(zip(res[form], res["converged"])):
             e = np.abs(a - r).max() / np.abs(r).max()
             assert e <= 1e-6, (form, q, e)
+
+
+def test_served_windows_match_oracle():
+    """Three windows served in a mix of eight (continuous batching, mixed
+    precision refined in FP64) against the CPU oracle's run of the same job
+    (preparation, initial function, rescale, 4 steps solved to relative
+    residual 1e-12): max-abs within 1e-6 of max |u|."""
+    import oracle as orc
+
+    pp, plain, mixed = S.default_params()
+    wins = S.make_windows(2000.0, 8)
+    stats = S.BatchServer(pp, mixed, steps=4, hbm_budget=8 << 30).run(wins)
+    assert stats["jobs"] == 8 and stats["max_concurrent"] >= 2
+    opp = orc.PrepareParams(K=pp.K, delta=pp.delta, vartheta=pp.vartheta, lam=pp.lam, ball_r=pp.ball_r,
+                            smooth_tau=pp.smooth_tau, smooth_steps=pp.smooth_steps,
+                            smooth_omega=pp.smooth_omega, smooth_tol=pp.smooth_tol)
+    osp = orc.StepParams(eps=mixed.eps, tau=mixed.tau, omega=1.5, tol=1e-12, ball_r=mixed.ball_r)
+    for q in (0, 3, 7):
+        img = wins[q].img
+        I0 = img.image.astype(np.float64) * pp.image_scale
+        ref = orc.run(img.n, I0, img.centres, img.seeds, opp, osp, steps=4, v=1.0, R=0.0, record=False)
+        u = ref["u_final"]
+        err = np.abs(wins[q].result - u).max() / np.abs(u).max()
+        assert err <= 1e-6, (q, img.n, err)
