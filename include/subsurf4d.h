@@ -25,7 +25,8 @@
  *  - Every pointer argument named "device" is device memory on the current
  *    HIP device; every other pointer is host memory.  The caller owns all
  *    memory.  The library calls no hipMalloc/hipFree: scratch space comes
- *    from the caller's workspace.  (The batched calls instantiate a HIP graph
+ *    from the caller's workspace (subsurf4d_step_noalloc: from a fixed device
+ *    array of the library).  (The batched calls instantiate a HIP graph
  *    per call, and on the legacy default stream run on one library-owned
  *    non-blocking stream per device.)
  *  - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
@@ -216,6 +217,27 @@ int subsurf4d_step(const subsurf4d_grid* grid, const double* G, const subsurf4d_
                    int32_t n_centres, const int32_t* owner, double* u,
                    const subsurf4d_step_params* params, subsurf4d_result* result,
                    void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * subsurf4d_step with the caller workspace replaced by a fixed device scratch
+ * array that the library holds on every device it runs on
+ * (SUBSURF4D_NOALLOC_SCRATCH_BYTES bytes, kept until the process ends; its
+ * address is looked up on the first call on each device).  Same arguments,
+ * results and status as subsurf4d_step otherwise.  A grid whose
+ * subsurf4d_workspace_bytes(grid, n_centres if rescale else 0, precision)
+ * exceeds the scratch returns SUBSURF4D_EWORKSPACE with nothing enqueued (the
+ * 24^3 x 8 grid needs 84 MiB in FP64, 107 MiB mixed).  The call allocates and
+ * frees no device memory.  Every call on one device shares that device's
+ * scratch and leaves its last contents there: calls that overlap in time on
+ * one device (other host threads, or unordered streams) race and give wrong
+ * results; each call initialises everything it reads.
+ */
+#define SUBSURF4D_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int subsurf4d_step_noalloc(const subsurf4d_grid* grid, const double* G, const subsurf4d_centre* centres,
+                           int32_t n_centres, const int32_t* owner, double* u,
+                           const subsurf4d_step_params* params, subsurf4d_result* result, void* stream);
 
 /*
  * The same step with Dirichlet data that changes in time (the boundary

@@ -29,7 +29,10 @@ EXPORTED = (
     "subsurf4d_last_error", "subsurf4d_version", "subsurf4d_timing", "subsurf4d_copy_probe",
     "subsurf4d_batch_workspace_bytes", "subsurf4d_batch_table_bytes", "subsurf4d_step_batched",
     "subsurf4d_prepare_workspace_bytes", "subsurf4d_prepare_batched", "subsurf4d_step_dirichlet",
+    "subsurf4d_step_noalloc",
 )
+
+NOALLOC_SCRATCH_BYTES = 128 << 20     # SUBSURF4D_NOALLOC_SCRATCH_BYTES
 
 
 class Grid(ctypes.Structure):
@@ -152,6 +155,8 @@ def lib():
                                      ctypes.POINTER(Result), P, SZ, P]
         L.subsurf4d_step_dirichlet.argtypes = [ctypes.POINTER(Grid), P, P, P, I, P, P,
                                                ctypes.POINTER(StepParamsC), ctypes.POINTER(Result), P, SZ, P]
+        L.subsurf4d_step_noalloc.argtypes = [ctypes.POINTER(Grid), P, P, I, P, P, ctypes.POINTER(StepParamsC),
+                                             ctypes.POINTER(Result), P]
         L.subsurf4d_solve.argtypes = [ctypes.POINTER(Grid), P, P, P, ctypes.POINTER(StepParamsC),
                                       ctypes.POINTER(Result), P, SZ, P]
         L.subsurf4d_status_string.argtypes = [ctypes.c_int]
@@ -304,6 +309,16 @@ def step(n, h, G, centres, n_centres, owner, u, params: StepParams, ws, stream=N
     _check(lib().subsurf4d_step(ctypes.byref(grid(n, h)), pG, pc, int(n_centres), po, pu,
                                 ctypes.byref(params.c()), ctypes.byref(res), _p(ws, "workspace"), _nb(ws),
                                 _stream(stream)))
+    return res.as_dict()
+
+
+def step_noalloc(n, h, G, centres, n_centres, owner, u, params: StepParams, stream=None) -> dict:
+    """subsurf4d_step on the library's fixed device scratch (no workspace
+    argument; no device memory is allocated by the call)."""
+    res = Result()
+    pG, pc, po, pu = _step_ptrs(n, G, centres, n_centres, owner, u)
+    _check(lib().subsurf4d_step_noalloc(ctypes.byref(grid(n, h)), pG, pc, int(n_centres), po, pu,
+                                        ctypes.byref(params.c()), ctypes.byref(res), _stream(stream)))
     return res.as_dict()
 
 

@@ -340,6 +340,66 @@ int subsurf4d_step(const subsurf4d_grid* grid, const double* G, const subsurf4d_
     SS4_GUARD_END
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device scratch of subsurf4d_step_noalloc: one fixed array in each device's
+// copy of the code object, in place of a caller workspace.  Host code never
+// passes `scratch` itself to a kernel (on the host it names a stand-in, not a
+// device address): the device address of each device's copy is looked up
+// once per device, with that device current, and kept.
+static __device__ __align__(256) unsigned char scratch[SUBSURF4D_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;
+
+int scratch_address(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "step_noalloc: current device");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "step_noalloc: address of the device scratch");
+        if (!p || reinterpret_cast<uintptr_t>(p) % 256 != 0)
+            return fail(SUBSURF4D_EDEVICE, "step_noalloc: device scratch is not 256-byte aligned");
+        it = g_scratch_ptr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int subsurf4d_step_noalloc(const subsurf4d_grid* grid, const double* G, const subsurf4d_centre* centres,
+                           int32_t n_centres, const int32_t* owner, double* u,
+                           const subsurf4d_step_params* params, subsurf4d_result* result, void* stream)
+{
+    SS4_GUARD_BEGIN
+    g_error.clear();
+    if (int rc = check_grid(grid)) return rc;
+    if (int rc = check_step_params(params)) return rc;
+    const int nc = params->rescale ? n_centres : 0;
+    WsPlan P;
+    if (nc < 0 || !plan_workspace(grid->n, nc, params->precision, &P))
+        return fail(SUBSURF4D_ESHAPE, "grid too large");
+    if (P.total > (size_t)SUBSURF4D_NOALLOC_SCRATCH_BYTES)
+        return fail(SUBSURF4D_EWORKSPACE, "step_noalloc: the grid needs more workspace than the library's "
+                                          "fixed device scratch (SUBSURF4D_NOALLOC_SCRATCH_BYTES); use "
+                                          "subsurf4d_step with a caller workspace");
+    void* ws = nullptr;
+    if (int rc = scratch_address(&ws)) return rc;
+    return step_common(grid, G, nullptr, centres, n_centres, owner, u, params, result, ws,
+                       (size_t)SUBSURF4D_NOALLOC_SCRATCH_BYTES, stream);
+    SS4_GUARD_END
+}
+
 int subsurf4d_step_dirichlet(const subsurf4d_grid* grid, const double* G, const double* u_dirichlet,
                              const subsurf4d_centre* centres, int32_t n_centres, const int32_t* owner, double* u,
                              const subsurf4d_step_params* params, subsurf4d_result* result, void* workspace,
