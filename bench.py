@@ -39,6 +39,7 @@ that keeps this error within 1e-6.
 from __future__ import annotations
 
 import argparse
+from dataclasses import replace
 import json
 import os
 import sys
@@ -87,42 +88,79 @@ def counter_traffic():
     return d
 
 
-def cpu_baseline(img, pp, sp, seconds):
-    """The oracle's red-black SOR (all host threads) on a bounded crop of the
-    same image: 128 x 128 x 96 voxels x 4 frames, one step's system."""
+def host_cpu_info():
+    """CPU model, physical cores and logical CPUs of this host, and the CPUs
+    this process may run on."""
+    model, cores = "unknown", set()
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                key, _, val = line.partition(":")
+                key, val = key.strip(), val.strip()
+                if key == "model name" and model == "unknown":
+                    model = val
+                elif key == "physical id":
+                    phys = val
+                elif key == "core id":
+                    core = val
+                elif not key and phys is not None and core is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count() or 0
+    return {"model": model, "physical_cores": len(cores) or None, "logical_cpus": os.cpu_count(),
+            "cpus_allowed": allowed}
+
+
+def cpu_baseline(img, sp, seconds):
+    """The oracle's red-black SOR timed on this host: a copy of the oracle built
+    here (-O3 -march=native -ffp-contract=off, OpenMP over the host threads) on
+    the first two frames of the same volume (512 x 512 x 96 x 2).  The system
+    is one step's, assembled by the oracle from the multi-seed initial function
+    with G = 1 (the cost of an SOR iteration does not depend on the coefficient
+    values).  Two runs of K1 < K2 iterations test the residual only before the
+    first and after the last iteration; their difference gives the time of
+    K2 - K1 iterations without the residuals and the set-up."""
+    import tempfile
+
     import numpy as np
 
     import oracle as orc
+    from oracle.build import build_oracle_native
 
-    n = (128, 128, 96, 4)
-    crop = np.ascontiguousarray(img.image[:n[3], :n[2], :n[1], :n[0]]).astype(np.float64) * pp.image_scale
-    cs = img.centres
-    sel = (cs["x"] < n[0]) & (cs["y"] < n[1]) & (cs["z"] < n[2]) & (cs["frame"] < n[3])
-    cs = cs[sel]
-    opp = orc.PrepareParams(K=pp.K, delta=pp.delta, vartheta=pp.vartheta, lam=pp.lam, ball_r=pp.ball_r,
-                            smooth_tau=pp.smooth_tau, smooth_steps=pp.smooth_steps)
-    prep = orc.prepare(n, crop, cs, opp)
-    u0 = orc.init_u(n, cs, 1.0, 8.0)
-    w = orc.rescale(n, u0, cs, sp.ball_r, prep["owner"])
-    coef, b = orc.assemble(n, prep["G"], w, 1.0, sp.eps, sp.tau)
+    orc.use_library(build_oracle_native(tempfile.mkdtemp(prefix="ss4_oracle_")))
+    n = (512, 512, 96, 2)
+    cs = img.centres[img.centres["frame"] < n[3]]
+    w = orc.init_u(n, cs, 1.0, 8.0)
+    G = np.ones((4,) + orc.padded_shape(n))
+    coef, b = orc.assemble(n, G, w, 1.0, sp.eps, sp.tau)
+    del G
     cells = n[0] * n[1] * n[2] * n[3]
-    t0 = time.perf_counter()
-    orc.sor(n, coef, b, w, sp.omega, 0.0, 1, orc.RB)
-    t1 = max(time.perf_counter() - t0, 1e-3)
-    iters = max(1, int(seconds / t1))
-    t0 = time.perf_counter()
-    orc.sor(n, coef, b, w, sp.omega, 0.0, iters, orc.RB)
-    dt = time.perf_counter() - t0
-    host = "unknown"
-    try:
-        with open("/proc/cpuinfo") as f:
-            host = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
-    except (OSError, StopIteration):
-        pass
-    return {"value": iters * cells / dt, "unit": "voxel-updates/s", "cores": orc.num_threads(),
-            "kind": "oracle", "host_cpu": host,
-            "sample": f"config-2 crop 128x128x96x4 ({cells} cells), one step's system, {iters} red-black "
-                      f"iterations incl. the oracle's per-iteration residual, {dt:.1f} s"}
+
+    def run(k):
+        t0 = time.perf_counter()
+        orc.sor(n, coef, b, w, sp.omega, 0.0, k, orc.RB, check_every=k)
+        return time.perf_counter() - t0
+
+    k1 = 2
+    t1 = run(k1)
+    t_it = max((run(k1 + 2) - t1) / 2.0, 1e-3)
+    k2 = k1 + max(4, int(seconds / t_it))
+    t1 = run(k1)
+    t2 = run(k2)
+    dt = max(t2 - t1, 1e-6)
+    host = host_cpu_info()
+    return {"value": (k2 - k1) * cells / dt, "unit": "voxel-updates/s", "cores": orc.num_threads(),
+            "kind": "oracle", "host": host,
+            "sample": f"512x512x96x2 frames of the config-2 volume ({cells} cells), one step's system (G = 1), "
+                      f"{k2 - k1} red-black iterations ({dt:.1f} s, the difference of runs of {k2} and {k1} "
+                      f"iterations), oracle built with -march=native on this host, {orc.num_threads()} OpenMP "
+                      f"threads on {host['cpus_allowed']} allowed CPUs"}
 
 
 def bench_batch(n_windows, steps, plain_sample, log_steps=False):
@@ -153,16 +191,30 @@ def bench_batch(n_windows, steps, plain_sample, log_steps=False):
     t_prep = time.perf_counter() - t0
     assert rc == 0, (rc, st)
     t0 = time.perf_counter()
-    passes = []
+    passes, mean_passes = [], []
     for st in range(steps):
         rc, res = B.step_batched(jobs, mixed, shared.table)
         passes.append(max(r["outer"] for r in res))
+        mean_passes.append(sum(r["outer"] for r in res) / len(res))
         if log_steps:
             log(f"[batch] step {st}: max passes {passes[-1]}")
     torch.cuda.synchronize()
     t_steps = time.perf_counter() - t0
     t_batch = t_prep + t_steps
     batched_u = [w.state.u.cpu().numpy() for w in wins[:plain_sample]]
+    # the same batch in FP64 (FP64 red-black sweeps of every window in each
+    # launch, stopping rule tested every 4 iterations), prepared again
+    fp64b = replace(plain, inner_sweeps=4)
+    B.step_batched(jobs, fp64b, shared.table)          # untimed: first FP64 batch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st = B.prepare_batched(jobs, pp, 1.0, 0.0, mixed.ball_r, shared.table)
+    assert rc == 0, (rc, st)
+    for _ in range(steps):
+        B.step_batched(jobs, fp64b, shared.table)
+    torch.cuda.synchronize()
+    t_fp64b = time.perf_counter() - t0
+    batched_fp64_u = [w.state.u.cpu().numpy() for w in wins[:plain_sample]]
     # plain per-job FP64 on a sample (same jobs, same initial function)
     for w in wins[plain_sample:]:
         w.state = None
@@ -195,12 +247,18 @@ def bench_batch(n_windows, steps, plain_sample, log_steps=False):
         "batched_step_ms": t_steps * 1e3 / steps,
         "batched_voxel_steps_per_s": cells * steps / t_steps,
         "refinement_passes_per_step_max": passes,
+        "refinement_passes_per_step_mean": mean_passes,
+        "batched_fp64_jobs_per_s": n_windows / t_fp64b,
+        "batched_fp64_note": "the same batch with FP64 sweeps (omega and tol of the plain form, stopping rule "
+                             "tested every 4 iterations), preparation included",
+        "mixed_vs_fp64_batched": t_fp64b / t_batch,
         "prepare_s_all_windows": t_prep,
         "plain_fp64_jobs_per_s": 1.0 / plain_per_job,
         "plain_sample_jobs": plain_sample,
         "speedup_jobs_per_s": (n_windows / t_batch) * plain_per_job,
         "max_rel_err_batched_vs_plain_fp64": rel(batched_u, plain_u),
         "max_rel_err_vs_converged": {"batched": rel(batched_u, conv_u), "plain_fp64": rel(plain_u, conv_u),
+                                     "batched_fp64": rel(batched_fp64_u, conv_u),
                                      "reference": "plain FP64 SOR to relative residual 1e-12, sample jobs"},
         "note": "both forms include preparation (thresholding, presmoothing, G, initial function and "
                 "rescale): one batched call for all windows, or one per job; device memory is allocated "
@@ -208,63 +266,85 @@ def bench_batch(n_windows, steps, plain_sample, log_steps=False):
     }
 
 
-def bench_serving(rates, count, plain_seconds, log=None, ref_jobs=400):
+def bench_serving(rates, count, plain_seconds, log=None, ref_jobs=40):
     """Config 5: Poisson arrivals of lognormal-size windows; continuous batching
-    against first-come-first-served plain FP64 per-job solves."""
+    (mixed precision) against first-come-first-served plain FP64 per-job
+    solves, at every arrival rate.  Job j's size and content do not depend on
+    the rate (its own seeds), so one set of images serves every rate and only
+    the arrival times change; the plain server is stopped after
+    `plain_seconds` per rate (its p50/p99 are over the jobs it served)."""
+    import numpy as np
     import torch
 
+    import synth
     from paper_2111_11866_amd import serve as S
 
-    import numpy as np
-
     pp, plain, mixed = S.default_params()
+    t0 = time.perf_counter()
+    _, sizes = synth.serving_stream(1.0, count)
+    imgs = synth.serving_windows(sizes)
+    if log:
+        log(f"[serve] {count} job images in {time.perf_counter() - t0:.1f}s")
+
+    def stream(rate):
+        t, _ = synth.serving_stream(rate, count)
+        return [S.Window(jid=q, arrival=float(t[q]), img=imgs[q]) for q in range(count)]
+
+    def keep(wins):
+        res = {w.jid: w.result for w in wins if w.result is not None and w.jid < ref_jobs}
+        for w in wins:
+            w.result = None
+        return res
+
+    def rel(a, ref):
+        e = [float(np.abs(a[j] - ref[j]).max() / max(np.abs(ref[j]).max(), 1e-300)) for j in ref if j in a]
+        return (max(e) if e else None), len(e)
+
+    # converged reference of the first jobs (FP64 SOR to relative residual 1e-12; untimed)
+    ref_wins = stream(1.0)[:ref_jobs]
+    S.PlainServer(pp, S.converged_params(plain), steps=20).run(ref_wins, realtime=False)
+    conv = keep(ref_wins)
+    # untimed warm-up of both servers (shape tuning, device memory pool)
+    batch_server = S.BatchServer(pp, mixed, steps=20, hbm_budget=96 << 30)
+    warm = stream(max(rates))[: min(count, 600)]
+    batch_server.run(warm, realtime=False)
+    keep(warm)
+    plain_server = S.PlainServer(pp, plain, steps=20)
+    warm = stream(max(rates))[:8]
+    plain_server.run(warm, realtime=False)
+    keep(warm)
+    torch.cuda.empty_cache()
     out = {}
     for rate in rates:
-        # untimed warm-up of both servers on another stream of the same law
-        # (the batched server's shape tuning and the device memory pool
-        # settle here, as they would in a long-running server)
-        batch_server = S.BatchServer(pp, mixed, steps=20, hbm_budget=96 << 30)
-        batch_server.run(S.make_windows(rate, count, seed=8), realtime=False)
-        plain_server = S.PlainServer(pp, plain, steps=20)
-        plain_server.run(S.make_windows(rate, 24, seed=8), realtime=False)
-        torch.cuda.empty_cache()
-        wins = S.make_windows(rate, count)
+        wins = stream(rate)
+        offered = count / max(w.arrival for w in wins)
         bs = batch_server.run(wins)
-        got = {w.jid: w.result for w in wins if w.result is not None}
+        got = keep(wins)
         del wins
         torch.cuda.empty_cache()
-        wins = S.make_windows(rate, count)
+        wins = stream(rate)
         ps = plain_server.run(wins, max_seconds=plain_seconds)
-        errs = [float(np.abs(got[w.jid] - w.result).max() / max(np.abs(w.result).max(), 1e-300))
-                for w in wins if w.result is not None and w.jid in got]
-        plain_res = {w.jid: w.result for w in wins if w.result is not None}
+        plain_res = keep(wins)
         del wins
         torch.cuda.empty_cache()
-        bs["max_rel_err_vs_plain_fp64"] = max(errs) if errs else None
-        bs["jobs_compared_with_plain"] = len(errs)
-        # converged reference for the first `ref_jobs` jobs (untimed, arrivals ignored)
-        ref = [w for w in S.make_windows(rate, count) if w.jid < ref_jobs]
-        S.PlainServer(pp, S.converged_params(plain), steps=20).run(ref, realtime=False)
-
-        def rel(res):
-            e = [float(np.abs(res[w.jid] - w.result).max() / max(np.abs(w.result).max(), 1e-300))
-                 for w in ref if w.jid in res]
-            return (max(e) if e else None), len(e)
-
-        (eb, nb), (ep, npl) = rel(got), rel(plain_res)
-        del ref, got, plain_res
-        torch.cuda.empty_cache()
-        bs["warmup_jobs"] = count
-        ps["warmup_jobs"] = 24
-        bs["max_rel_err_vs_converged"] = eb
-        bs["jobs_compared_with_converged"] = nb
-        ps["max_rel_err_vs_converged"] = ep
-        ps["jobs_compared_with_converged"] = npl
+        bs["offered_jobs_per_s"] = ps["offered_jobs_per_s"] = offered
+        bs["keeps_up"] = bool(bs["jobs_per_s"] >= 0.9 * offered)
+        ps["keeps_up"] = bool(ps["jobs_per_s"] >= 0.9 * offered and ps.get("unserved", 0) == 0)
+        bs["max_rel_err_vs_plain_fp64"], bs["jobs_compared_with_plain"] = rel(got, plain_res)
+        bs["max_rel_err_vs_converged"], bs["jobs_compared_with_converged"] = rel(got, conv)
+        ps["max_rel_err_vs_converged"], ps["jobs_compared_with_converged"] = rel(plain_res, conv)
+        ps["stopped_after_s"] = plain_seconds
         out[str(rate)] = {"batched": bs, "plain_fp64": ps}
+        del got, plain_res
         if log:
-            log(f"[serve] rate {rate}/s: batched {bs['jobs_per_s']:.1f} jobs/s p50 {bs['p50_latency_s']:.3f}s "
-                f"p99 {bs['p99_latency_s']:.3f}s | plain {ps['jobs_per_s']:.1f} jobs/s "
-                f"p50 {ps['p50_latency_s']:.3f}s p99 {ps['p99_latency_s']:.3f}s")
+            log(f"[serve] rate {rate}/s (offered {offered:.0f}): batched {bs['jobs_per_s']:.1f} jobs/s "
+                f"p50 {bs['p50_latency_s']:.3f}s p99 {bs['p99_latency_s']:.3f}s keeps up {bs['keeps_up']} | "
+                f"plain {ps['jobs_per_s']:.1f} jobs/s p50 {ps['p50_latency_s']:.3f}s "
+                f"p99 {ps['p99_latency_s']:.3f}s ({ps['jobs']} served, {ps.get('unserved', 0)} not)")
+    out["jobs_per_rate"] = count
+    out["note"] = ("latency from arrival to the result on the host; the plain FP64 server is stopped after "
+                   f"{plain_seconds:.0f} s per rate, its jobs/s and latencies are over the jobs it served; "
+                   "errors relative to max |u| of the job")
     return out
 
 
@@ -285,10 +365,11 @@ def main():
     ap.add_argument("--windows", type=int, default=2048, help="batched workload size (0: skip)")
     ap.add_argument("--window-steps", type=int, default=20)
     ap.add_argument("--plain-sample", type=int, default=24)
-    ap.add_argument("--serving-rate", type=float, default=1000.0, help="0: skip the serving run")
-    ap.add_argument("--serving-jobs", type=int, default=400)
-    ap.add_argument("--serving-sweep", action="store_true",
-                    help="arrival rates 200..5000 jobs/s with 2000 jobs each (long)")
+    ap.add_argument("--serving-rates", type=str, default="200,500,1000,2000,5000",
+                    help="comma-separated arrival rates (jobs/s); empty: skip the serving run")
+    ap.add_argument("--serving-jobs", type=int, default=2000, help="jobs per arrival rate")
+    ap.add_argument("--plain-seconds", type=float, default=8.0,
+                    help="the plain FP64 server is stopped after this many seconds per rate")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -476,7 +557,7 @@ def main():
     del src, dst
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
-        out["cpu_baseline"] = cpu_baseline(img, pp, sp, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(img, sp, args.cpu_seconds)
         log(f"[bench] cpu baseline in {time.perf_counter() - t0:.1f}s")
     del job
     torch.cuda.empty_cache()
@@ -485,10 +566,11 @@ def main():
         out["batched_windows"] = bench_batch(args.windows, args.window_steps, args.plain_sample)
         log(f"[bench] batched windows in {time.perf_counter() - t0:.1f}s: {out['batched_windows']}")
         torch.cuda.empty_cache()
-    if args.serving_sweep:
-        out["serving"] = bench_serving([200, 500, 1000, 2000, 5000], 2000, 60.0, log=log)
-    elif args.serving_rate > 0:
-        out["serving"] = bench_serving([args.serving_rate], args.serving_jobs, 15.0, log=log)
+    rates = [float(r) for r in args.serving_rates.split(",") if r.strip()]
+    if rates:
+        t0 = time.perf_counter()
+        out["serving"] = bench_serving(rates, args.serving_jobs, args.plain_seconds, log=log)
+        log(f"[bench] serving sweep in {time.perf_counter() - t0:.1f}s")
     print(json.dumps(out), flush=True)
 
 

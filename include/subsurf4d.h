@@ -26,13 +26,17 @@
  *    HIP device; every other pointer is host memory.  The caller owns all
  *    memory.  The library calls no hipMalloc/hipFree: scratch space comes
  *    from the caller's workspace (subsurf4d_step_noalloc: from a fixed device
- *    array of the library).  (The batched calls instantiate a HIP graph
- *    per call, and on the legacy default stream run on one library-owned
- *    non-blocking stream per device.)
+ *    array of the library).  (The batched calls keep one HIP graph
+ *    executable per stream, and on the legacy default stream run on one
+ *    library-owned non-blocking stream per device.)
  *  - `stream` is a hipStream_t (NULL = default stream).  Work is enqueued on
- *    it.  Calls that iterate to a tolerance (prepare, step, solve) read the
- *    device-side convergence state between chunks of iterations and therefore
- *    synchronise `stream`; when they return, every result they write is final.
+ *    it.  By default the calls that iterate to a tolerance (prepare, step,
+ *    solve, the batched calls) read the device-side convergence state between
+ *    chunks of iterations and therefore synchronise `stream`; when they
+ *    return, every result they write is final.  With SUBSURF4D_FLAG_ASYNC the
+ *    step and solve calls only enqueue work (no host synchronisation, no host
+ *    read of device memory, capturable in a HIP graph) and write their
+ *    outcome to a device-accessible result.
  *  - Errors: argument and shape checks happen before anything is enqueued and
  *    return a negative status.  A HIP failure returns SUBSURF4D_EDEVICE.  No
  *    C++ exception crosses this interface.  subsurf4d_last_error() gives a
@@ -119,6 +123,19 @@ typedef struct {
  * 256-cell items, or 256-slot columns marching through the frames. */
 #define SUBSURF4D_FLAG_SWEEP_FLAT 2
 #define SUBSURF4D_FLAG_SWEEP_MARCH 4
+/* subsurf4d_step_params.flags: enqueue-only step / solve (subsurf4d_step,
+ * subsurf4d_step_dirichlet, subsurf4d_step_noalloc, subsurf4d_solve).  The
+ * call checks its arguments, enqueues every launch up to the iteration cap and
+ * returns 0 without synchronising: FP64 enqueues 2*max_iter + 1 half-sweeps
+ * (fixed_iters in place of max_iter when set), MIXED max_iter/inner_sweeps + 1
+ * refinement passes; launches after the stopping rule has been met return at
+ * once, so max_iter bounds the cost and should be set near the expected
+ * count.  `result` (NULL allowed) must then be device memory or pinned host
+ * memory: the last kernel of the call writes the outcome there, including
+ * SUBSURF4D_NOT_CONVERGED and SUBSURF4D_ENONFINITE, which the return value
+ * does not report.  Only kernel launches are enqueued (no memset or copy), so
+ * the call can be captured in a HIP graph and replayed. */
+#define SUBSURF4D_FLAG_ASYNC 8
 
 /* Outcome of a solve.  Iterations are full red-black iterations. */
 typedef struct {
@@ -208,7 +225,8 @@ int subsurf4d_assemble(const subsurf4d_grid* grid, const double* G, const double
  * R_k <= tol ||b||_2 and return u^(k); after max_iter iterations return
  * u^(max_iter) with SUBSURF4D_NOT_CONVERGED.  Then, if params->rescale, apply
  * the local rescaling with (centres, owner).  u is overwritten with the new
- * level (ghosts unchanged).  result (host) receives the outcome.
+ * level (ghosts unchanged).  result (host; device-accessible with
+ * SUBSURF4D_FLAG_ASYNC; may be NULL) receives the outcome.
  * precision MIXED: FP32 red-black sweeps on BF16-stored coefficients inside
  * an FP64 iterative refinement to refine_tol (the FP64 residual uses the FP64
  * operator).
@@ -278,17 +296,34 @@ int subsurf4d_solve(const subsurf4d_grid* grid, const double* coef, const double
 int subsurf4d_copy_probe(const void* src, void* dst, size_t bytes, int32_t reps, double* ms, void* stream);
 
 /*
+ * Read-dominated bandwidth probe (the sweeps read about 11 streams per one
+ * written): dst[i] = sum over r < reads of src[r*n + i], n = bytes/16 16-byte
+ * elements, once untimed and then `reps` times between two HIP events on
+ * `stream`; *ms (host) receives the mean time of one pass, which moves
+ * (reads + 1) * bytes.  src (device) holds reads * bytes, dst (device) bytes,
+ * both 16-byte aligned, not overlapping; reads in [1, 16].  Synchronises
+ * `stream`.  Not part of the method.
+ */
+int subsurf4d_stream_probe(const void* src, void* dst, size_t bytes, int32_t reads, int32_t reps, double* ms,
+                           void* stream);
+
+/*
  * Batched time step over many independent windows (the per-nucleus windows
- * the paper cuts around cells, Sec. 4), in mixed precision.  Each job is one
- * window with its own grid, G, u, owner map, centres and workspace; every job
- * gets exactly what subsurf4d_step with precision SUBSURF4D_MIXED computes
- * for it (assembly, FP64-refined FP32/BF16 red-black SOR to refine_tol, local
- * rescaling), but all jobs advance together: each kernel launch processes the
- * work items of every unfinished job, and the refinement pass (FP64
- * residual, `inner_sweeps` red-black iterations, update) is captured once as
- * a HIP graph and replayed until every job has met its stopping rule.  A job's
- * result does not depend on the other jobs of the batch (per-job reductions in
- * a fixed order).
+ * the paper cuts around cells, Sec. 4).  Each job is one window with its own
+ * grid, G, u, owner map, centres and workspace; all jobs advance together:
+ * each kernel launch processes the work items of every unfinished job.
+ * precision SUBSURF4D_MIXED: every job gets what subsurf4d_step with
+ * SUBSURF4D_MIXED computes for it (assembly, FP64-refined FP32/BF16
+ * red-black SOR to refine_tol, local rescaling); a refinement pass is
+ * `inner_sweeps` FP32 red-black iterations, the update and the FP64
+ * residual.  precision SUBSURF4D_FP64: FP64 red-black SOR of the system
+ * itself to tol, a pass being `inner_sweeps` iterations followed by the FP64
+ * residual (the stopping rule is tested every inner_sweeps iterations;
+ * check_every is ignored).  The pass is captured as a HIP graph whose
+ * executable the library keeps per (device, stream) and updates with each
+ * call's arguments; passes are replayed in chunks until every job has met its
+ * stopping rule (a pass after that does no work).  A job's result does not
+ * depend on the other jobs of the batch (per-job reductions in a fixed order).
  */
 typedef struct {
     subsurf4d_grid grid;
@@ -313,8 +348,10 @@ size_t subsurf4d_batch_table_bytes(int32_t n_jobs);
 
 /*
  * Advance every job by one time step.  jobs (host array of n_jobs), params
- * (precision must be SUBSURF4D_MIXED; fixed_iters is ignored), results (host
- * array of n_jobs, may be NULL), table (device, >= subsurf4d_batch_table_bytes).
+ * (SUBSURF4D_MIXED or SUBSURF4D_FP64, inner_sweeps in [1, 1024];
+ * fixed_iters is ignored; SUBSURF4D_FLAG_ASYNC is refused), results (host
+ * array of n_jobs, may be NULL; iterations = passes * inner_sweeps), table
+ * (device, >= subsurf4d_batch_table_bytes).
  * Synchronises `stream`.  Returns SUBSURF4D_NOT_CONVERGED if any job hit its
  * cap, SUBSURF4D_ENONFINITE if any job failed (see each job's result).
  * n_jobs = 0 is an empty batch: SUBSURF4D_OK, nothing enqueued (jobs and
@@ -361,6 +398,60 @@ typedef struct {
 int subsurf4d_prepare_batched(const subsurf4d_batch_prepare_job* jobs, int32_t n_jobs,
                               const subsurf4d_prepare_params* params, double v, double R, double ball_r,
                               int32_t* statuses, void* table, size_t table_bytes, void* stream);
+
+/*
+ * Cell tracking from the segmentation (Sec. 5, cell tracking based on the 4D
+ * segmentation).  A voxel of frame l is segmented when u >= level; a cell is
+ * a set of segmented voxels of one frame connected through shared faces,
+ * named by the smallest interior index of its voxels.  For every cell voxel
+ * the squared distance (voxel units) to the nearest voxel of its frame
+ * outside the cell, the outside of the image counting as outside; the cell's
+ * centre is its voxel of largest distance (ties: smallest index).  Backward
+ * link of a cell of frame l > 0 (the backtracking of Sec. 5): the cell of
+ * frame l-1 holding the centre's voxel (kind 1); else the cell of frame l-1
+ * overlapping the most of this cell's voxels moved to frame l-1 (ties:
+ * smallest name; kind 2); else none (prev -1, kind 0).
+ */
+typedef struct {
+    int32_t name;     /* smallest interior index of the cell's voxels */
+    int32_t frame;    /* 0-based frame */
+    int32_t centre;   /* interior index of the centre voxel */
+    int32_t dist2;    /* squared distance of the centre to the nearest voxel outside the cell */
+    int32_t prev;     /* name of the linked cell of the previous frame, -1 if none */
+    int32_t kind;     /* 0 none, 1 centre, 2 overlap, 3 joined (subsurf4d_track_join) */
+} subsurf4d_cell;
+
+/* Bytes of device workspace of subsurf4d_track for `capacity` cells (host-only;
+ * 0 if the grid has 2^31 or more interior voxels). */
+size_t subsurf4d_track_workspace_bytes(const subsurf4d_grid* grid, int32_t capacity);
+
+/*
+ * Cells, distances, centres and backward links of the segmentation u (device,
+ * padded).  label (device, interior int32, out): cell name or -1; dist2
+ * (device, interior int32, out): squared distance, 0 outside cells; cells
+ * (host, `capacity` records, out): one per cell in increasing name order;
+ * *n_cells (host, out): the number of cells (also when it exceeds capacity,
+ * which returns SUBSURF4D_EWORKSPACE).  Synchronises `stream`.
+ */
+int subsurf4d_track(const subsurf4d_grid* grid, const double* u, double level, int32_t* label, int32_t* dist2,
+                    subsurf4d_cell* cells, int32_t capacity, int32_t* n_cells, void* workspace,
+                    size_t workspace_bytes, void* stream);
+
+/*
+ * Joining of partial trajectories (host-only; Sec. 5, last step).  A cell that
+ * no cell of the next frame links to ends a partial trajectory, which runs
+ * back along the links to a cell without one.  A partial trajectory T whose
+ * first cell lies in frame f > 0 is joined after a partial trajectory S ending
+ * in frame f-1 when T's first centre moved back by T's first displacement
+ * (kept as is for a single cell) lies within `radius` voxels of S's last
+ * centre, or S's last centre moved on by S's last displacement lies within
+ * `radius` of T's first centre; T takes the nearest such S (squared distance;
+ * ties: the smaller name of S's last cell), each S joins at most once, and
+ * the T are taken in the order of the names of their first cells.  A join
+ * sets the link of T's first cell to S's last cell with kind 3.  cells (host,
+ * n_cells records from subsurf4d_track, updated in place).
+ */
+int subsurf4d_track_join(const subsurf4d_grid* grid, subsurf4d_cell* cells, int32_t n_cells, double radius);
 
 /* Static text for a status code. */
 const char* subsurf4d_status_string(int status);

@@ -38,6 +38,14 @@ def build(force: bool = True) -> str:
     return build_oracle(force=force)
 
 
+def use_library(path: str) -> None:
+    """Load the oracle from another build of the same source (the CPU-baseline
+    timing build for the host); later calls go through it."""
+    global _lib, _LIB_PATH
+    _LIB_PATH = path
+    _lib = None
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -355,3 +363,124 @@ def eoc_run(N, steps, T=0.0625, L=1.25, omega=1.5, tol=1e-11, grid="cell", eps=N
         w = ex.copy()                      # next level's gradient ghosts: exact solution at t_s
         w[inner] = u[inner]
     return float(np.sqrt(err2)), its
+
+
+# ------------------------------------------------------------ cell tracking
+
+CELL_DTYPE = np.dtype([("name", "<i4"), ("frame", "<i4"), ("centre", "<i4"), ("d2", "<i4"), ("prev", "<i4"),
+                       ("kind", "<i4")])
+
+
+def track_label(n, u_padded, level):
+    """Cells of every frame (Sec. 5): 6-connected sets of voxels with u >= level,
+    each voxel labelled with its cell's smallest interior index, -1 outside."""
+    L = lib()
+    L.oracle_track_label.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]
+    u = np.ascontiguousarray(u_padded, dtype=np.float64)
+    out = np.empty(interior_shape(n), dtype=np.int32)
+    L.oracle_track_label(_ptr(_dims(n)), _ptr(u), float(level), _ptr(out))
+    return out
+
+
+def track_dist2(n, label):
+    """Squared distance of every cell voxel to the nearest voxel outside its cell."""
+    L = lib()
+    L.oracle_track_dist2.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lab = np.ascontiguousarray(label, dtype=np.int32)
+    out = np.empty(interior_shape(n), dtype=np.int32)
+    L.oracle_track_dist2(_ptr(_dims(n)), _ptr(lab), _ptr(out))
+    return out
+
+
+def track_cells(n, label, d2, capacity=1 << 16):
+    """Per-cell records (name, frame, centre, d2, prev, kind) in name order."""
+    L = lib()
+    L.oracle_track_cells.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_int]
+    L.oracle_track_cells.restype = ctypes.c_int
+    rec = np.zeros((capacity, 6), dtype=np.int32)
+    k = L.oracle_track_cells(_ptr(_dims(n)), _ptr(np.ascontiguousarray(label, dtype=np.int32)),
+                             _ptr(np.ascontiguousarray(d2, dtype=np.int32)), _ptr(rec), int(capacity))
+    if k < 0:
+        raise RuntimeError("more cells than the capacity")
+    return np.ascontiguousarray(rec[:k]).view(CELL_DTYPE).reshape(k)
+
+
+def voxel_xyz(n, index):
+    """(x, y, z) voxel coordinates of an interior index (frame dropped)."""
+    n1, n2, n3, _ = n
+    q = int(index) % (n1 * n2 * n3)
+    return (q % n1, (q // n1) % n2, q // (n1 * n2))
+
+
+def track_join(n, cells, radius):
+    """Trajectories from the backward links (Sec. 5): every cell that no cell of
+    the next frame links to ends a partial trajectory, which follows the links
+    back to a cell without one.  A partial trajectory T whose first cell is in
+    frame f > 0 is then joined after the partial trajectory S that ends in frame
+    f-1 when the tangent prolongation of one reaches the other: T's first point
+    moved back by its first displacement (2 c0 - c1, or c0 for a single cell)
+    lies within `radius` of S's last point, or S's last point moved on by its
+    last displacement lies within `radius` of T's first point.  T takes the
+    candidate with the smallest squared distance (ties: the smallest name of
+    S's last cell); each S is joined at most once, T in order of the name of
+    its first cell.  Returns a list of trajectories, each a list of cell
+    names from the first frame to the last."""
+    by_name = {int(c["name"]): c for c in cells}
+    has_next = {int(c["prev"]) for c in cells if c["prev"] >= 0}
+    partial = []
+    for c in sorted(cells, key=lambda c: int(c["name"])):
+        if int(c["name"]) in has_next:
+            continue
+        chain = [int(c["name"])]
+        while by_name[chain[-1]]["prev"] >= 0:
+            chain.append(int(by_name[chain[-1]]["prev"]))
+        partial.append(chain[::-1])
+
+    def xyz(name):
+        return np.array(voxel_xyz(n, by_name[name]["centre"]), dtype=np.int64)
+
+    ends = {}
+    for t, ch in enumerate(partial):
+        ends.setdefault(int(by_name[ch[-1]]["frame"]), []).append(t)
+    joined_after = {}
+    used = set()
+    for t in sorted(range(len(partial)), key=lambda t: partial[t][0]):
+        first = partial[t][0]
+        f = int(by_name[first]["frame"])
+        if f == 0:
+            continue
+        c0 = xyz(first)
+        back = 2 * c0 - xyz(partial[t][1]) if len(partial[t]) > 1 else c0
+        best = None
+        for s in ends.get(f - 1, []):
+            if s in used or s == t:
+                continue
+            last = partial[s][-1]
+            e0 = xyz(last)
+            fwd = 2 * e0 - xyz(partial[s][-2]) if len(partial[s]) > 1 else e0
+            dd = min(int(np.sum((back - e0) ** 2)), int(np.sum((fwd - c0) ** 2)))
+            if dd <= radius * radius and (best is None or (dd, last) < (best[0], best[1])):
+                best = (dd, last, s)
+        if best is not None:
+            used.add(best[2])
+            joined_after[t] = best[2]
+    heads = [t for t in range(len(partial)) if t not in used]
+    out = []
+    for t in heads:
+        chain = list(partial[t])
+        cur = t
+        while cur in joined_after:
+            cur = joined_after[cur]
+            chain = partial[cur] + chain
+        out.append(chain)
+    out.sort(key=lambda ch: ch[0])
+    return out
+
+
+def track(n, u_padded, level=0.5, radius=0.0):
+    """The whole tracking of Sec. 5: labels, distances, cells with links, trajectories."""
+    label = track_label(n, u_padded, level)
+    d2 = track_dist2(n, label)
+    cells = track_cells(n, label, d2)
+    return dict(label=label, d2=d2, cells=cells, tracks=track_join(n, cells, radius))

@@ -25,5 +25,16 @@ def build_oracle(force: bool = True) -> str:
     return LIB
 
 
+def build_oracle_native(out_dir: str) -> str:
+    """A copy of the oracle compiled for the host it runs on (-march=native),
+    for timing the CPU baseline there; the tests use the generic build."""
+    os.makedirs(out_dir, exist_ok=True)
+    out = os.path.join(out_dir, "liboracle_subsurf4d_native.so")
+    cmd = ["gcc", "-O3", "-march=native", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-o", out, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
 if __name__ == "__main__":
     print(build_oracle())

@@ -385,6 +385,29 @@ void oracle_face_g(const int *n, double h, double K, double delta, double varthe
 void oracle_init_u(const int *n, const oracle_centre *cs, int nc, double v, double R, double *u)
 {
     memset(u, 0, padded_count(n) * sizeof(double));
+    if (R > 0.0) {
+        /* with the cut-off every profile is 0 beyond distance R of its seed, and
+         * all values are >= 0: the maximum over the seeds is the maximum over
+         * the seeds whose R-ball holds the cell, taken seed by seed over a box
+         * around each ball (cells in no ball keep 0) */
+        for (int m = 0; m < nc; ++m) {
+            const oracle_centre *c = &cs[m];
+            if (c->frame < 0 || c->frame >= n[3]) continue;
+            const long l = c->frame + 1;
+            long lo[3], hi[3];
+            ball_box(n, c, R, lo, hi);
+            for (long k = lo[2]; k <= hi[2]; ++k)
+                for (long j = lo[1]; j <= hi[1]; ++j)
+                    for (long i = lo[0]; i <= hi[0]; ++i) {
+                        const double dd = sqrt(dist2(c, i, j, k));
+                        double val = 1.0 / (dd + v) - 1.0 / (R + v);
+                        if (val < 0.0) val = 0.0;
+                        double *p = &u[pidx(n, i, j, k, l)];
+                        if (val > *p) *p = val;
+                    }
+        }
+        return;
+    }
     for (long l = 1; l <= n[3]; ++l)
         for (long k = 1; k <= n[2]; ++k)
             for (long j = 1; j <= n[1]; ++j)
@@ -622,4 +645,157 @@ int oracle_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------ cell tracking */
+
+/*
+ * Cell tracking from the 4D segmentation (Sec. 5, "Cell tracking based on 4D
+ * segmentation").  Readings where the section is silent:
+ *  - a voxel of frame l is segmented when u >= level (u after the last step;
+ *    the level is a parameter, 0.5 for rescaled u in [0,1]);
+ *  - a "segmented cell" is a set of segmented voxels of one frame connected
+ *    through shared faces (6-neighbourhood); it is named by the smallest
+ *    interior index of its voxels (a name unique over all frames);
+ *  - "distance from the segmented cell boundary" is the Euclidean distance to
+ *    the nearest voxel of the same frame outside the cell, the region outside
+ *    the image counting as outside; the centre is the voxel where it is
+ *    largest, ties to the smallest index.
+ *
+ * Labels (interior int32): the cell name, -1 for voxels outside every cell.
+ * Flood fill from every unlabelled segmented voxel in increasing index order,
+ * so the first voxel reached is the smallest of its cell.
+ */
+void oracle_track_label(const int *n, const double *u, double level, int32_t *label)
+{
+    const size_t ni = (size_t)n[0] * n[1] * n[2] * n[3];
+    long *queue = (long *)malloc(ni * sizeof(long) * 4 + 4 * sizeof(long));
+    for (size_t q = 0; q < ni; ++q) label[q] = -1;
+    for (long l = 1; l <= n[3]; ++l)
+        for (long k = 1; k <= n[2]; ++k)
+            for (long j = 1; j <= n[1]; ++j)
+                for (long i = 1; i <= n[0]; ++i) {
+                    const size_t q0 = iidx(n, i, j, k, l);
+                    if (label[q0] >= 0 || !(u[pidx(n, i, j, k, l)] >= level)) continue;
+                    const int32_t name = (int32_t)q0;
+                    size_t head = 0, tail = 0;
+                    label[q0] = name;
+                    queue[tail++] = i; queue[tail++] = j; queue[tail++] = k;
+                    while (head < tail) {
+                        const long ci = queue[head], cj = queue[head + 1], ck = queue[head + 2];
+                        head += 3;
+                        const long nb[6][3] = {{ci - 1, cj, ck}, {ci + 1, cj, ck}, {ci, cj - 1, ck},
+                                               {ci, cj + 1, ck}, {ci, cj, ck - 1}, {ci, cj, ck + 1}};
+                        for (int s = 0; s < 6; ++s) {
+                            const long a = nb[s][0], b = nb[s][1], c = nb[s][2];
+                            if (a < 1 || a > n[0] || b < 1 || b > n[1] || c < 1 || c > n[2]) continue;
+                            const size_t qn = iidx(n, a, b, c, l);
+                            if (label[qn] >= 0 || !(u[pidx(n, a, b, c, l)] >= level)) continue;
+                            label[qn] = name;
+                            queue[tail++] = a; queue[tail++] = b; queue[tail++] = c;
+                        }
+                    }
+                }
+    free(queue);
+}
+
+/*
+ * Squared distance (voxel units) of every voxel of a cell to the nearest voxel
+ * of its frame outside the cell, by brute force over the frame and its
+ * one-voxel outer shell (outside the image); 0 for voxels in no cell.
+ * O(cells' voxels x frame voxels): small grids only.
+ */
+void oracle_track_dist2(const int *n, const int32_t *label, int32_t *d2)
+{
+    const size_t ni = (size_t)n[0] * n[1] * n[2] * n[3];
+    for (size_t q = 0; q < ni; ++q) d2[q] = 0;
+#pragma omp parallel for schedule(dynamic)
+    for (long l = 1; l <= n[3]; ++l)
+        for (long k = 1; k <= n[2]; ++k)
+            for (long j = 1; j <= n[1]; ++j)
+                for (long i = 1; i <= n[0]; ++i) {
+                    const size_t q = iidx(n, i, j, k, l);
+                    const int32_t own = label[q];
+                    if (own < 0) continue;
+                    long best = -1;
+                    for (long c = 0; c <= n[2] + 1; ++c)
+                        for (long b = 0; b <= n[1] + 1; ++b)
+                            for (long a = 0; a <= n[0] + 1; ++a) {
+                                const int outside = a < 1 || a > n[0] || b < 1 || b > n[1] || c < 1 || c > n[2];
+                                if (!outside && label[iidx(n, a, b, c, l)] == own) continue;
+                                const long dd = (a - i) * (a - i) + (b - j) * (b - j) + (c - k) * (c - k);
+                                if (best < 0 || dd < best) best = dd;
+                            }
+                    d2[q] = (int32_t)best;
+                }
+}
+
+/*
+ * One record per cell, in increasing name order: name, frame, centre (interior
+ * index of the voxel of largest d2, ties to the smallest index), its d2, and
+ * the link to the previous frame by the backtracking of Sec. 5: the cell of
+ * frame l-1 that contains the centre's voxel moved to frame l-1 (kind 1);
+ * otherwise the cell of frame l-1 that overlaps most voxels of this cell moved
+ * to frame l-1, ties to the smallest name (kind 2); otherwise none (-1, kind 0).
+ * rec: capacity x 6 int32 (name, frame, centre, d2, prev, kind).  Returns the
+ * number of cells, or -1 if it exceeds the capacity.
+ */
+int oracle_track_cells(const int *n, const int32_t *label, const int32_t *d2, int32_t *rec, int capacity)
+{
+    const size_t ni = (size_t)n[0] * n[1] * n[2] * n[3];
+    const size_t fsz = (size_t)n[0] * n[1] * n[2];
+    int32_t *slot = (int32_t *)malloc(ni * sizeof(int32_t));     /* record of the cell a name names */
+    int nc = 0;
+    for (size_t q = 0; q < ni; ++q) {
+        slot[q] = -1;
+        if (label[q] != (int32_t)q) continue;          /* q names its cell */
+        if (nc >= capacity) { free(slot); return -1; }
+        int32_t *r = rec + 6 * nc;
+        r[0] = (int32_t)q;
+        r[1] = (int32_t)(q / fsz);
+        r[2] = (int32_t)q;
+        r[3] = d2[q];
+        r[4] = -1;
+        r[5] = 0;
+        slot[q] = nc;
+        ++nc;
+    }
+    /* centres: scan voxels in increasing index; strict '>' keeps the smallest */
+    for (size_t q = 0; q < ni; ++q) {
+        if (label[q] < 0) continue;
+        int32_t *r = rec + 6 * slot[label[q]];
+        if (d2[q] > r[3]) { r[3] = d2[q]; r[2] = (int32_t)q; }
+    }
+    int32_t *cand = (int32_t *)malloc(fsz * sizeof(int32_t));
+    long *count = (long *)malloc(fsz * sizeof(long));
+    for (int c = 0; c < nc; ++c) {
+        int32_t *r = rec + 6 * c;
+        if (r[1] == 0) continue;
+        const int32_t below = label[(size_t)r[2] - fsz];
+        if (below >= 0) { r[4] = below; r[5] = 1; continue; }
+        /* overlap counts with the cells of the previous frame: a list of
+         * (candidate, count) pairs over this cell's voxels */
+        int nk = 0;
+        for (size_t q = (size_t)r[1] * fsz; q < (size_t)(r[1] + 1) * fsz; ++q) {
+            if (label[q] != r[0]) continue;
+            const int32_t b = label[q - fsz];
+            if (b < 0) continue;
+            int t = 0;
+            while (t < nk && cand[t] != b) ++t;
+            if (t == nk) { cand[nk] = b; count[nk] = 0; ++nk; }
+            ++count[t];
+        }
+        int32_t best = -1;
+        long best_count = 0;
+        for (int t = 0; t < nk; ++t)
+            if (count[t] > best_count || (count[t] == best_count && cand[t] < best)) {
+                best = cand[t];
+                best_count = count[t];
+            }
+        if (best >= 0) { r[4] = best; r[5] = 2; }
+    }
+    free(cand);
+    free(count);
+    free(slot);
+    return nc;
 }

@@ -29,7 +29,8 @@ EXPORTED = (
     "subsurf4d_last_error", "subsurf4d_version", "subsurf4d_timing", "subsurf4d_copy_probe",
     "subsurf4d_batch_workspace_bytes", "subsurf4d_batch_table_bytes", "subsurf4d_step_batched",
     "subsurf4d_prepare_workspace_bytes", "subsurf4d_prepare_batched", "subsurf4d_step_dirichlet",
-    "subsurf4d_step_noalloc",
+    "subsurf4d_step_noalloc", "subsurf4d_stream_probe", "subsurf4d_track_workspace_bytes", "subsurf4d_track",
+    "subsurf4d_track_join",
 )
 
 NOALLOC_SCRATCH_BYTES = 128 << 20     # SUBSURF4D_NOALLOC_SCRATCH_BYTES
@@ -58,6 +59,7 @@ class StepParamsC(ctypes.Structure):
 FLAG_NO_GRAPH = 1
 FLAG_SWEEP_FLAT = 2
 FLAG_SWEEP_MARCH = 4
+FLAG_ASYNC = 8
 
 
 class BatchJobC(ctypes.Structure):
@@ -72,6 +74,15 @@ class BatchPrepareJobC(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("seeds", ctypes.c_void_p), ("G", ctypes.c_void_p),
                 ("owner", ctypes.c_void_p), ("u", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
+
+
+class CellC(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_int32), ("frame", ctypes.c_int32), ("centre", ctypes.c_int32),
+                ("dist2", ctypes.c_int32), ("prev", ctypes.c_int32), ("kind", ctypes.c_int32)]
+
+
+CELL_DTYPE = np.dtype([("name", "<i4"), ("frame", "<i4"), ("centre", "<i4"), ("dist2", "<i4"), ("prev", "<i4"),
+                       ("kind", "<i4")])
 
 
 class Result(ctypes.Structure):
@@ -166,6 +177,7 @@ def lib():
         L.subsurf4d_timing.argtypes = [I, P, P, P, P]
         L.subsurf4d_timing.restype = None
         L.subsurf4d_copy_probe.argtypes = [P, P, SZ, I, P, P]
+        L.subsurf4d_stream_probe.argtypes = [P, P, SZ, I, I, P, P]
         L.subsurf4d_batch_workspace_bytes.argtypes = [ctypes.POINTER(Grid), I]
         L.subsurf4d_batch_workspace_bytes.restype = SZ
         L.subsurf4d_prepare_workspace_bytes.argtypes = [ctypes.POINTER(Grid), I]
@@ -177,6 +189,11 @@ def lib():
         L.subsurf4d_prepare_batched.argtypes = [ctypes.POINTER(BatchPrepareJobC), I,
                                                 ctypes.POINTER(PrepareParamsC), D, D, D,
                                                 ctypes.POINTER(ctypes.c_int32), P, SZ, P]
+        L.subsurf4d_track_workspace_bytes.argtypes = [ctypes.POINTER(Grid), I]
+        L.subsurf4d_track_workspace_bytes.restype = SZ
+        L.subsurf4d_track.argtypes = [ctypes.POINTER(Grid), P, D, P, P, ctypes.POINTER(CellC), I,
+                                      ctypes.POINTER(ctypes.c_int32), P, SZ, P]
+        L.subsurf4d_track_join.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(CellC), I, D]
         _lib = L
     return _lib
 
@@ -343,6 +360,60 @@ def solve(n, h, coef, b, u, params: StepParams, ws, stream=None) -> dict:
     return res.as_dict()
 
 
+RESULT_BYTES = ctypes.sizeof(Result)
+
+
+def result_tensor(device="cuda"):
+    """Device buffer for the outcome of an enqueue-only call."""
+    import torch
+
+    return torch.zeros(RESULT_BYTES, dtype=torch.uint8, device=device)
+
+
+def result_dict(t) -> dict:
+    """Outcome written by an enqueue-only call (copies to the host, which
+    waits for the call's work)."""
+    raw = bytes(t.cpu().numpy().tobytes())
+    return Result.from_buffer_copy(raw).as_dict()
+
+
+def step_async(n, h, G, centres, n_centres, owner, u, params: StepParams, ws, result=None, stream=None):
+    """Enqueue-only subsurf4d_step (SUBSURF4D_FLAG_ASYNC): nothing is
+    synchronised; `result` (device tensor of RESULT_BYTES bytes, or None)
+    receives the outcome when the stream reaches it."""
+    from dataclasses import replace
+
+    sp = replace(params, flags=params.flags | FLAG_ASYNC)
+    pG, pc, po, pu = _step_ptrs(n, G, centres, n_centres, owner, u)
+    pres = _p(result, "result", "uint8", RESULT_BYTES)
+    _check(lib().subsurf4d_step(ctypes.byref(grid(n, h)), pG, pc, int(n_centres), po, pu, ctypes.byref(sp.c()),
+                                ctypes.cast(pres, ctypes.POINTER(Result)) if pres is not None else None,
+                                _p(ws, "workspace"), _nb(ws), _stream(stream)))
+
+
+def solve_async(n, h, coef, b, u, params: StepParams, ws, result=None, stream=None):
+    """Enqueue-only subsurf4d_solve (SUBSURF4D_FLAG_ASYNC)."""
+    from dataclasses import replace
+
+    sp = replace(params, flags=params.flags | FLAG_ASYNC)
+    ni, npd = _cells(n)
+    pres = _p(result, "result", "uint8", RESULT_BYTES)
+    _check(lib().subsurf4d_solve(ctypes.byref(grid(n, h)), _p(coef, "coef", "float64", 64 * ni),
+                                 _p(b, "b", "float64", 8 * ni), _p(u, "u", "float64", 8 * npd),
+                                 ctypes.byref(sp.c()),
+                                 ctypes.cast(pres, ctypes.POINTER(Result)) if pres is not None else None,
+                                 _p(ws, "workspace"), _nb(ws), _stream(stream)))
+
+
+def stream_probe(src, dst, reads, reps=10, stream=None) -> float:
+    """Mean ms of one pass dst = sum of `reads` chunks of src (each the size of dst)."""
+    ms = ctypes.c_double(0.0)
+    nbytes = _nb(dst)
+    _check(lib().subsurf4d_stream_probe(_p(src, "src", None, reads * nbytes), _p(dst, "dst"), nbytes, int(reads),
+                                        int(reps), ctypes.byref(ms), _stream(stream)))
+    return ms.value
+
+
 def timing(op: int = 3) -> dict:
     """Sweep instrumentation: op 0 disable, 1 enable, 2 reset, 3 read."""
     ms = ctypes.c_double(0.0)
@@ -423,6 +494,33 @@ def prepare_batched(jobs, pp: PrepareParams, v, R, ball_r, table, stream=None):
     return rc, list(st)
 
 
+def track(n, u, level, capacity=1 << 16, join_radius=None, label=None, dist2=None, ws=None, stream=None):
+    """Cells of the segmentation u (device, padded) with their centres and
+    backward links (subsurf4d_track), optionally joined into trajectories
+    (subsurf4d_track_join with `join_radius`).  Returns (cells as a numpy
+    record array, label tensor, dist2 tensor)."""
+    import torch
+
+    ni, npd = _cells(n)
+    dev = u.device
+    label = torch.empty(interior_shape(n), dtype=torch.int32, device=dev) if label is None else label
+    dist2 = torch.empty(interior_shape(n), dtype=torch.int32, device=dev) if dist2 is None else dist2
+    if ws is None:
+        nb = int(lib().subsurf4d_track_workspace_bytes(ctypes.byref(grid(n)), int(capacity)))
+        if nb == 0:
+            raise Subsurf4dError(ESHAPE, "unsupported grid for tracking")
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    cells = (CellC * max(int(capacity), 1))()
+    k = ctypes.c_int32(0)
+    _check(lib().subsurf4d_track(ctypes.byref(grid(n)), _p(u, "u", "float64", 8 * npd), float(level),
+                                 _p(label, "label", "int32", 4 * ni), _p(dist2, "dist2", "int32", 4 * ni), cells,
+                                 int(capacity), ctypes.byref(k), _p(ws, "workspace"), _nb(ws), _stream(stream)))
+    if join_radius is not None:
+        _check(lib().subsurf4d_track_join(ctypes.byref(grid(n)), cells, k.value, float(join_radius)))
+    out = np.frombuffer(bytes(cells)[: k.value * ctypes.sizeof(CellC)], dtype=CELL_DTYPE).copy()
+    return out, label, dist2
+
+
 def version() -> str:
     return lib().subsurf4d_version().decode()
 
@@ -465,6 +563,24 @@ class Job:
         init_u(self.n, self.h, self.seeds, self.ns, v, R, self.u)
         if do_rescale:
             rescale(self.n, self.h, self.centres, self.nc, ball_r, self.owner, self.u, self.ws)
+
+    def save(self, path):
+        """Checkpoint of the job's device state (u, G, owner map) to one .npz
+        file; with the image, centres and seeds it is all a job needs to
+        resume."""
+        np.savez(path, u=self.u.cpu().numpy(), G=self.G.cpu().numpy(), owner=self.owner.cpu().numpy(),
+                 n=np.asarray(self.n), h=np.asarray(self.h))
+
+    def load(self, path):
+        """Resume from a checkpoint written by save() for the same grid."""
+        import torch
+
+        with np.load(path, allow_pickle=False) as z:
+            if tuple(int(v) for v in z["n"]) != self.n or float(z["h"]) != self.h:
+                raise ValueError("checkpoint of another grid")
+            self.u.copy_(torch.from_numpy(z["u"]))
+            self.G.copy_(torch.from_numpy(z["G"]))
+            self.owner.copy_(torch.from_numpy(z["owner"]))
 
     def step(self, sp: StepParams):
         from dataclasses import replace

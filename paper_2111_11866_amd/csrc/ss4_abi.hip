@@ -122,6 +122,7 @@ static_assert(sizeof(subsurf4d_step_params) == 80, "step params layout");
 static_assert(sizeof(subsurf4d_result) == 32, "result layout");
 static_assert(sizeof(subsurf4d_batch_job) == 80, "batch job layout");
 static_assert(sizeof(subsurf4d_batch_prepare_job) == 104, "batch prepare job layout");
+static_assert(sizeof(subsurf4d_cell) == 24, "cell record layout");
 
 namespace {
 
@@ -171,7 +172,8 @@ int check_step_params(const subsurf4d_step_params* p)
         if (p->inner_sweeps < 1 || p->inner_sweeps > 1024)
             return fail(SUBSURF4D_EINVAL, "inner_sweeps must be in [1, 1024]");
     }
-    const int known = SUBSURF4D_FLAG_NO_GRAPH | SUBSURF4D_FLAG_SWEEP_FLAT | SUBSURF4D_FLAG_SWEEP_MARCH;
+    const int known = SUBSURF4D_FLAG_NO_GRAPH | SUBSURF4D_FLAG_SWEEP_FLAT | SUBSURF4D_FLAG_SWEEP_MARCH |
+                      SUBSURF4D_FLAG_ASYNC;
     if (p->flags & ~known) return fail(SUBSURF4D_EINVAL, "unknown flags");
     if ((p->flags & SUBSURF4D_FLAG_SWEEP_FLAT) && (p->flags & SUBSURF4D_FLAG_SWEEP_MARCH))
         return fail(SUBSURF4D_EINVAL, "at most one sweep shape flag");
@@ -322,8 +324,10 @@ int step_common(const subsurf4d_grid* grid, const double* G, const double* ub, c
     WsPlan P;
     if (!plan_workspace(grid->n, nc, params->precision, &P)) return fail(SUBSURF4D_ESHAPE, "grid too large");
     if (int rc = check_ws(P, workspace, workspace_bytes)) return rc;
+    // enqueue-only calls write the outcome on the device, into `result` if given
     subsurf4d_result tmp;
-    return run_step(P, grid->h, G, ub, centres, nc, owner, u, *params, result ? result : &tmp, workspace,
+    const bool async = (params->flags & SUBSURF4D_FLAG_ASYNC) != 0;
+    return run_step(P, grid->h, G, ub, centres, nc, owner, u, *params, result || async ? result : &tmp, workspace,
                     static_cast<hipStream_t>(stream));
 }
 
@@ -428,7 +432,22 @@ int subsurf4d_solve(const subsurf4d_grid* grid, const double* coef, const double
     if (!plan_workspace(grid->n, 0, SUBSURF4D_FP64, &P)) return fail(SUBSURF4D_ESHAPE, "grid too large");
     if (int rc = check_ws(P, workspace, workspace_bytes)) return rc;
     subsurf4d_result tmp;
-    return run_solve(P, coef, b, u, *params, result ? result : &tmp, workspace, static_cast<hipStream_t>(stream));
+    const bool async = (params->flags & SUBSURF4D_FLAG_ASYNC) != 0;
+    return run_solve(P, coef, b, u, *params, result || async ? result : &tmp, workspace,
+                     static_cast<hipStream_t>(stream));
+    SS4_GUARD_END
+}
+
+int subsurf4d_stream_probe(const void* src, void* dst, size_t bytes, int32_t reads, int32_t reps, double* ms,
+                           void* stream)
+{
+    SS4_GUARD_BEGIN
+    g_error.clear();
+    if (!src || !dst || !ms || reps < 1 || reads < 1 || reads > 16) return fail(SUBSURF4D_EINVAL, "bad arguments");
+    if (bytes == 0 || bytes % 16 != 0) return fail(SUBSURF4D_EINVAL, "bytes must be a positive multiple of 16");
+    if (reinterpret_cast<uintptr_t>(src) % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0)
+        return fail(SUBSURF4D_EINVAL, "buffers must be 16-byte aligned");
+    return run_stream_probe(src, dst, bytes, reads, reps, ms, static_cast<hipStream_t>(stream));
     SS4_GUARD_END
 }
 
@@ -467,7 +486,10 @@ int subsurf4d_step_batched(const subsurf4d_batch_job* jobs, int32_t n_jobs, cons
     if (int rc = check_step_params(params)) return rc;
     if (n_jobs == 0) return SUBSURF4D_OK;
     if (!jobs || n_jobs < 0 || !table) return fail(SUBSURF4D_EINVAL, "bad batch arguments");
-    if (params->precision != SUBSURF4D_MIXED) return fail(SUBSURF4D_EINVAL, "the batched step is mixed precision");
+    if (params->flags & SUBSURF4D_FLAG_ASYNC)
+        return fail(SUBSURF4D_EINVAL, "the batched step synchronises (no SUBSURF4D_FLAG_ASYNC)");
+    if (params->inner_sweeps < 1 || params->inner_sweeps > 1024)
+        return fail(SUBSURF4D_EINVAL, "inner_sweeps must be in [1, 1024]");
     if (reinterpret_cast<uintptr_t>(table) % 256 != 0) return fail(SUBSURF4D_EINVAL, "table must be 256-byte aligned");
     for (int q = 0; q < n_jobs; ++q) {
         const subsurf4d_batch_job& j = jobs[q];
@@ -509,6 +531,52 @@ int subsurf4d_prepare_batched(const subsurf4d_batch_prepare_job* jobs, int32_t n
     }
     return run_batch_prepare(jobs, n_jobs, *params, v, R, ball_r, statuses, table, table_bytes,
                              static_cast<hipStream_t>(stream));
+    SS4_GUARD_END
+}
+
+size_t subsurf4d_track_workspace_bytes(const subsurf4d_grid* grid, int32_t capacity)
+{
+    try {
+        if (!grid || capacity < 0) return 0;
+        for (int d = 0; d < 4; ++d)
+            if (grid->n[d] < 1 || grid->n[d] > (1 << 20)) return 0;
+        const int64_t N = (int64_t)grid->n[0] * grid->n[1] * grid->n[2] * grid->n[3];
+        if (N >= ((int64_t)1 << 31)) return 0;
+        return track_workspace_bytes(grid->n, capacity);
+    } catch (...) {
+        return 0;
+    }
+}
+
+int subsurf4d_track(const subsurf4d_grid* grid, const double* u, double level, int32_t* label, int32_t* dist2,
+                    subsurf4d_cell* cells, int32_t capacity, int32_t* n_cells, void* workspace,
+                    size_t workspace_bytes, void* stream)
+{
+    SS4_GUARD_BEGIN
+    g_error.clear();
+    if (int rc = check_grid(grid)) return rc;
+    if (!u || !label || !dist2 || !n_cells || capacity < 0 || (capacity > 0 && !cells))
+        return fail(SUBSURF4D_EINVAL, "NULL argument");
+    if (!std::isfinite(level)) return fail(SUBSURF4D_EINVAL, "level must be finite");
+    const int64_t N = (int64_t)grid->n[0] * grid->n[1] * grid->n[2] * grid->n[3];
+    if (N >= ((int64_t)1 << 31)) return fail(SUBSURF4D_ESHAPE, "tracking names voxels by 32-bit indices");
+    if (!workspace) return fail(SUBSURF4D_EINVAL, "workspace is NULL");
+    if (workspace_bytes < track_workspace_bytes(grid->n, capacity))
+        return fail(SUBSURF4D_EWORKSPACE, "workspace too small (see subsurf4d_track_workspace_bytes)");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(SUBSURF4D_EINVAL, "workspace must be 256-byte aligned");
+    return run_track(grid->n, u, level, label, dist2, cells, capacity, n_cells, workspace,
+                     static_cast<hipStream_t>(stream));
+    SS4_GUARD_END
+}
+
+int subsurf4d_track_join(const subsurf4d_grid* grid, subsurf4d_cell* cells, int32_t n_cells, double radius)
+{
+    SS4_GUARD_BEGIN
+    g_error.clear();
+    if (int rc = check_grid(grid)) return rc;
+    if (n_cells < 0 || (n_cells > 0 && !cells)) return fail(SUBSURF4D_EINVAL, "bad cells");
+    if (!(radius >= 0.0) || !std::isfinite(radius)) return fail(SUBSURF4D_EINVAL, "radius must be >= 0");
+    return run_track_join(grid->n, cells, n_cells, radius);
     SS4_GUARD_END
 }
 

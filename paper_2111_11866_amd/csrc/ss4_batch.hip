@@ -403,6 +403,60 @@ __global__ __launch_bounds__(kBlock) void kb_sweep_tm(BTable T)
     });
 }
 
+// FP64 half-sweep of colour COLOR on the step's system itself (batched FP64
+// form), frame-marching shape as kb_sweep_tm: x <- omega*(b + sum_f c_f x_f)/D
+// + (1-omega)*x on the colour-split iterate, whose ghost slots hold the
+// Dirichlet data.  Same arithmetic as the single-job FP64 sweep.
+template <int COLOR>
+__global__ __launch_bounds__(kBlock) void kb_sweep64_tm(BTable T)
+{
+    const double om = T.omega64, om1 = 1.0 - T.omega64;
+    for_runs(T.act_colf, T.act_jobs, *T.n_act, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
+        const BJob J = T.jobs[jb];
+        const uint32_t sy = J.rsu, sz = (uint32_t)J.p2 * J.rsu, st = sz * (uint32_t)J.p3;
+        SS4_GLOBAL double* own = gbl(COLOR ? J.xb : J.xr);
+        SS4_GLOBAL const double* oth = gbl(static_cast<const double*>(COLOR ? J.xr : J.xb));
+        SS4_GLOBAL const double* coef = gbl(static_cast<const double*>(J.coef));
+        const uint32_t nqf = (uint32_t)J.nqf;
+        for (uint32_t item = i0; item < i1; item += step) {
+            const uint32_t qf = item * kItem + threadIdx.x;
+            if (qf >= nqf) continue;
+            const uint32_t r = fdiv(qf, J.mg_half);
+            const int m = (int)(qf - r * (uint32_t)J.half);
+            const uint32_t r2 = fdiv(r, J.mg_n2);
+            const int j = (int)(r - r2 * (uint32_t)J.n2) + 1;
+            const int k = (int)r2 + 1;
+            const uint32_t u0 = ((uint32_t)k * J.p2 + (uint32_t)j) * J.rsu + 1 + m;   // row (j,k,l=0)
+            double Bm = oth[u0];
+            double Bc = oth[u0 + st];
+            for (int l = 1; l <= J.n4; ++l) {
+                const uint32_t ui = u0 + (uint32_t)l * st;
+                const double Bp = oth[ui + st];
+                const int par = (COLOR + j + k + l) & 1;
+                const int cnt = par ? (J.n1 + 1) >> 1 : J.n1 >> 1;
+                if (m < cnt) {
+                    const uint32_t q = (uint32_t)(l - 1) * nqf + qf;
+                    SS4_GLOBAL const double* cf = coef + bctile(J, COLOR, q);
+                    const double c0 = cf[0], c1 = cf[kTileSlots], c2 = cf[2 * kTileSlots];
+                    const double c3 = cf[3 * kTileSlots], c4 = cf[4 * kTileSlots];
+                    const double c5 = cf[5 * kTileSlots], c6 = cf[6 * kTileSlots];
+                    const double c7 = cf[7 * kTileSlots];
+                    const double xo = oth[par ? ui - 1 : ui + 1];
+                    double sum = cf[8 * kTileSlots];
+                    sum += c0 * (par ? xo : Bc) + c1 * (par ? Bc : xo);
+                    sum += c2 * oth[ui - sy] + c3 * oth[ui + sy];
+                    sum += c4 * oth[ui - sz] + c5 * oth[ui + sz];
+                    sum += c6 * Bm + c7 * Bp;
+                    const double D = ((((((((1.0 + c0) + c1) + c2) + c3) + c4) + c5) + c6) + c7);
+                    own[ui] = om * (sum / D) + om1 * own[ui];
+                }
+                Bm = Bc;
+                Bc = Bp;
+            }
+        }
+    });
+}
+
 // x += d for unfinished jobs (the next pass's first iteration does not read d).
 __global__ __launch_bounds__(kBlock) void kb_update(BTable T)
 {
@@ -655,6 +709,51 @@ hipStream_t side_stream()
     return st;
 }
 
+// Executable graph of one refinement pass, kept per (device, stream): the
+// pass is captured on every call (host-side work only) and the kept
+// executable is updated in place with the new capture's kernel arguments and
+// launch sizes; it is instantiated anew only when the update is refused (a
+// different number of launches: other m or precision).
+template <typename F>
+int pass_graph(hipStream_t s, F&& enqueue, hipGraphExec_t* out)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, hipStream_t>, hipGraphExec_t> kept;
+    int dev = 0;
+    SS4_HIP(hipGetDevice(&dev));
+    hipGraph_t graph = nullptr;
+    SS4_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    enqueue();
+    SS4_HIP(hipStreamEndCapture(s, &graph));
+    std::lock_guard<std::mutex> g(mu);
+    const auto key = std::make_pair(dev, s);
+    auto it = kept.find(key);
+    hipError_t e = hipSuccess;
+    if (it != kept.end()) {
+        hipGraphExecUpdateResult how = hipGraphExecUpdateError;
+        hipGraphNode_t bad = nullptr;
+        e = hipGraphExecUpdate(it->second, graph, &bad, &how);
+        if (e != hipSuccess || how != hipGraphExecUpdateSuccess) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(it->second);
+            kept.erase(it);
+            it = kept.end();
+        }
+    }
+    if (it == kept.end()) {
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(e, "batched: graph instantiation");
+        }
+        it = kept.emplace(key, exec).first;
+    }
+    (void)hipGraphDestroy(graph);
+    *out = it->second;
+    return 0;
+}
+
 int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf4d_step_params& sp,
                       subsurf4d_result* results, void* table, size_t table_bytes, hipStream_t s);
 
@@ -726,8 +825,10 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
     T.n_act = T.active + 2;
     T.n_jobs = n_jobs;
     const int m = sp.inner_sweeps;
+    const bool fp64 = sp.precision == SUBSURF4D_FP64;
     T.max_outer = sp.max_iter / m > 1 ? sp.max_iter / m : 1;
     T.omega = (float)sp.omega;
+    T.omega64 = sp.omega;
     SS4_HIP(hipMemcpyAsync(T.jobs, hj.data(), sizeof(BJob) * n_jobs, hipMemcpyHostToDevice, s));
     SS4_HIP(hipMemcpyAsync(T.asm_start, asm_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
     SS4_HIP(hipMemcpyAsync(T.int_start, int_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
@@ -740,13 +841,13 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
     const int g_up = resident_grid(reinterpret_cast<const void*>(&kb_update));
     const dim3 g_zero(64, n_jobs < 65535 ? n_jobs : 65535);
 
-    kb_init<<<(n_jobs + 255) / 256, 256, 0, s>>>(T, sp.refine_tol, T.max_outer);
+    kb_init<<<(n_jobs + 255) / 256, 256, 0, s>>>(T, fp64 ? sp.tol : sp.refine_tol, T.max_outer);
     const int g_dec = n_jobs < 4096 ? n_jobs : 4096;
     kb_split_u<<<g_up, kBlock, 0, s>>>(T);
     kb_assemble<<<g_asm, kBlock, 0, s>>>(T);
     kb_assemble_decide<<<g_dec, kBlock, 0, s>>>(T);
     kb_compact<<<1, kScan, 0, s>>>(T);
-    kb_zero_d<<<g_zero, 256, 0, s>>>(T);
+    if (!fp64) kb_zero_d<<<g_zero, 256, 0, s>>>(T);
     SS4_LAUNCHED("batched: assemble");
 
     // Autotuner of the inner sweep's 4D tile shape and launch shape: the first
@@ -777,7 +878,10 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
             }
         }
     };
-    if (forced) {
+    const int g64 = fp64 ? resident_grid(reinterpret_cast<const void*>(&kb_sweep64_tm<0>)) : 0;
+    if (fp64) {
+        // the FP64 sweep has one shape (frame-marching) at the resident grid
+    } else if (forced) {
         shape = forced - 1;
         g_sw = shape == 0 ? resident_grid(reinterpret_cast<const void*>(&kb_sweep<0, false>))
                           : resident_grid(reinterpret_cast<const void*>(&kb_sweep_tm<0, false>));
@@ -839,30 +943,39 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
 
     // one refinement pass = m inner iterations, update, FP64 residual of the
     // new iterate, per-job decision, compaction (the assembly supplied the
-    // residual and the decision of the initial iterate); captured once as a
-    // graph and replayed until every job has finished
+    // residual and the decision of the initial iterate).  FP64 form: m FP64
+    // red-black iterations of the system itself, then the same residual,
+    // decision and compaction (the stopping rule is tested every m
+    // iterations).  A pass after every job has finished does no work, so
+    // passes are enqueued in chunks and the host reads the number of
+    // unfinished jobs once per chunk.
     const bool eager = (sp.flags & SUBSURF4D_FLAG_NO_GRAPH) != 0;
     auto enqueue_pass = [&]() {
-        for (int it = 0; it < m; ++it) sweep_pair(shape, g_sw, it == 0);
-        kb_update<<<g_up, kBlock, 0, s>>>(T);
+        if (fp64) {
+            for (int it = 0; it < m; ++it) {
+                kb_sweep64_tm<0><<<g64, kBlock, 0, s>>>(T);
+                kb_sweep64_tm<1><<<g64, kBlock, 0, s>>>(T);
+            }
+        } else {
+            for (int it = 0; it < m; ++it) sweep_pair(shape, g_sw, it == 0);
+            kb_update<<<g_up, kBlock, 0, s>>>(T);
+        }
         kb_next_pass<<<1, 64, 0, s>>>(T);
         kb_residual<<<g_res, kBlock, 0, s>>>(T);
         kb_residual_decide<<<g_dec, kBlock, 0, s>>>(T);
         kb_compact<<<1, kScan, 0, s>>>(T);
     };
-    hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     if (!eager) {
-        SS4_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        enqueue_pass();
-        SS4_HIP(hipStreamEndCapture(s, &graph));
-        SS4_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        int rcg = pass_graph(s, enqueue_pass, &exec);
+        if (rcg) return rcg;
     }
 
     int active = n_jobs;
     SS4_HIP(hipMemcpyAsync(&active, T.active, sizeof(int), hipMemcpyDeviceToHost, s));
     SS4_HIP(hipStreamSynchronize(s));
     int passes = 0;
+    int chunk = 2;
     int rc = 0;
     while (active > 0) {
         if (passes > T.max_outer + 1) {
@@ -871,19 +984,20 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
             break;
         }
         hipError_t e = hipSuccess;
-        if (eager) {
-            enqueue_pass();
-            e = hipGetLastError();
-        } else {
-            e = hipGraphLaunch(exec, s);
+        for (int c = 0; c < chunk && e == hipSuccess; ++c) {
+            if (eager) {
+                enqueue_pass();
+                e = hipGetLastError();
+            } else {
+                e = hipGraphLaunch(exec, s);
+            }
         }
         if (e == hipSuccess) e = hipMemcpyAsync(&active, T.active, sizeof(int), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) { rc = hip_fail(e, "batched: refinement pass"); break; }
-        ++passes;
+        passes += chunk;
+        chunk = chunk < 8 ? 2 * chunk : 8;
     }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
     if (rc) return rc;
 
     kb_unsplit<<<g_up, kBlock, 0, s>>>(T);

@@ -60,8 +60,9 @@ struct BTable {
     int64_t* act_colf;    // prefix of nitf over act_jobs
     int n_jobs;
     int max_outer;
-    float omega;
+    float omega;          // mixed: relaxation of the FP32 correction sweeps
     int pad;
+    double omega64;       // FP64: relaxation of the FP64 sweeps
 };
 
 size_t al256(size_t x);

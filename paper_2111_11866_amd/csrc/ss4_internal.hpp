@@ -80,6 +80,7 @@ int run_unsplit(const WsPlan& P, double* u, void* ws, hipStream_t s);
 int launch_assembly(const WsPlan& P, double h, const double* G, const double* w, const double* ub,
                     const subsurf4d_step_params& sp, void* coef16, void* ws, hipStream_t s);
 int run_copy_probe(const void* src, void* dst, size_t bytes, int reps, double* ms, hipStream_t s);
+int run_stream_probe(const void* src, void* dst, size_t bytes, int reads, int reps, double* ms, hipStream_t s);
 
 // batched windows (batch.hip)
 size_t batch_job_bytes(const int32_t n[4], int32_t nc);
@@ -89,6 +90,13 @@ int run_batch_prepare(const subsurf4d_batch_prepare_job* jobs, int n_jobs, const
                       hipStream_t s);
 int run_batch_step(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf4d_step_params& sp,
                    subsurf4d_result* results, void* table, size_t table_bytes, hipStream_t s);
+
+// cell tracking (track.hip)
+constexpr int64_t kTrackTableEntries = (int64_t)1 << 24;   // overlap table entries (at least)
+size_t track_workspace_bytes(const int32_t n[4], int32_t capacity);
+int run_track(const int32_t n[4], const double* u, double level, int32_t* lab, int32_t* d2, subsurf4d_cell* cells,
+              int32_t capacity, int32_t* n_cells, void* ws, hipStream_t s);
+int run_track_join(const int32_t n[4], subsurf4d_cell* cells, int32_t nc, double radius);
 
 // mixed precision (mixed.hip)
 int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w, const double* ub,

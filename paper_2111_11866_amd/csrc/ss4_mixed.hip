@@ -47,6 +47,7 @@ __global__ __launch_bounds__(kBlock) void k_mx_residual(MxArgs a)
 {
     __shared__ double lds[4];
     __shared__ int flag;
+    if (a.C->done) return;      // enqueue-only calls: a pass after the decision
     const Layout& L = a.L;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int ntm = (L.half + 63) >> 6;
@@ -137,6 +138,7 @@ __device__ __forceinline__ float mx_cell(uint4 w, float rhs, float xl, float xr,
 template <int COLOR, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_mx_sweep(MxArgs a)
 {
+    if (a.C->done) return;
     const Layout& L = a.L;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int ntm = (L.half + 63) >> 6;
@@ -200,6 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_mx_sweep(MxArgs a)
 // iteration does not read d).
 __global__ __launch_bounds__(kBlock) void k_mx_update(MxArgs a)
 {
+    if (a.C->done) return;
     const Layout& L = a.L;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int ntm = (L.half + 63) >> 6;
@@ -274,6 +277,28 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
     const int res_g = resident_grid(reinterpret_cast<const void*>(&k_mx_sweep<0, false>)) / 2;
     const int grid_cols = (int)(((ncol < res_g ? ncol : res_g) + kXcd - 1) / kXcd * kXcd);
 
+    auto enqueue_sweeps = [&]() {
+        k_mx_sweep<0, true><<<grid_cols, kBlock, 0, s>>>(a);
+        k_mx_sweep<1, true><<<grid_cols, kBlock, 0, s>>>(a);
+        for (int it = 1; it < m; ++it) {
+            k_mx_sweep<0, false><<<grid_cols, kBlock, 0, s>>>(a);
+            k_mx_sweep<1, false><<<grid_cols, kBlock, 0, s>>>(a);
+        }
+    };
+    if (sp.flags & SUBSURF4D_FLAG_ASYNC) {
+        // enqueue-only: every pass up to the cap; the kernels of a pass after
+        // the residual's decision return at once
+        for (int pass = 0; pass <= max_outer; ++pass) {
+            a.pass = pass;
+            k_mx_residual<<<grid_res, kBlock, 0, s>>>(a);
+            if (pass == max_outer) break;
+            enqueue_sweeps();
+            k_mx_update<<<grid_rows, kBlock, 0, s>>>(a);
+        }
+        SS4_LAUNCHED("mixed: refinement passes");
+        return 0;
+    }
+
     Ctrl hc;
     SS4_HIP(hipMemcpyAsync(&hc, C, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     SS4_HIP(hipStreamSynchronize(s));
@@ -287,12 +312,7 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
         SS4_HIP(hipStreamSynchronize(s));
         if (hc.done) break;
         timer.begin();
-        k_mx_sweep<0, true><<<grid_cols, kBlock, 0, s>>>(a);
-        k_mx_sweep<1, true><<<grid_cols, kBlock, 0, s>>>(a);
-        for (int it = 1; it < m; ++it) {
-            k_mx_sweep<0, false><<<grid_cols, kBlock, 0, s>>>(a);
-            k_mx_sweep<1, false><<<grid_cols, kBlock, 0, s>>>(a);
-        }
+        enqueue_sweeps();
         timer.end();
         k_mx_update<<<grid_rows, kBlock, 0, s>>>(a);
         SS4_LAUNCHED("mixed: inner sweeps");

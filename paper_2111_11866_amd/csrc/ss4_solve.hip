@@ -33,17 +33,139 @@ struct AsmArgs {
     Ctrl* C;
 };
 
-// One thread per padded cell.  Ghost cells only copy the new level's Dirichlet
-// value into the colour-split u; interior cells compute the 8 coefficients
-// from the 33-point neighbourhood of w and G on the 8 faces.
+// Per-block partials of ||b||^2 and of the initial residual, and (last block)
+// the decision on iterate 0.
+__device__ __forceinline__ void assembly_decide(const AsmArgs& a, double acc_b, double acc_r, double* lds, int* flagp)
+{
+    int& flag = *flagp;
+    const double bb = block_sum(acc_b, lds);
+    const double rr = block_sum(acc_r, lds);
+    if (threadIdx.x == 0) { a.part_a[blockIdx.x] = bb; a.part_b[blockIdx.x] = rr; }
+    if (!arrive_last(&a.C->arrive[0], gridDim.x, &flag)) return;
+    const double B2 = sum_partials(a.part_a, gridDim.x, lds);
+    const double R2 = sum_partials(a.part_b, gridDim.x, lds);
+    if (threadIdx.x == 0) {
+        Ctrl* C = a.C;
+        C->bn = sqrt(B2);
+        const double R = sqrt(R2);
+        C->rel_res = C->bn > 0.0 ? R / C->bn : R;
+        C->iterations = 0;
+        C->final_red = 0;
+        if (!(R2 < INFINITY) || !(B2 < INFINITY)) { C->status = SUBSURF4D_ENONFINITE; C->done = 1; }
+        else if (R <= C->tol * C->bn) C->done = 1;
+        else if (C->max_iter <= 0) { C->status = SUBSURF4D_NOT_CONVERGED; C->done = 1; }
+        C->arrive[0] = 0;
+    }
+}
+
+// Coefficients, right-hand side and residual of the initial iterate of one
+// interior cell p = (i,j,k,l) from the 33-point neighbourhood of w and G on
+// its 8 faces; the colour-split tiles (MODE kSplit) or the natural arrays
+// (kNatural) receive them.  Shared by both assembly kernels, so the
+// coefficients do not depend on the visiting order.
+template <int MODE, typename WAt, typename GAt>
+__device__ __forceinline__ void assemble_cell(const AsmArgs& a, int64_t p, int i, int j, int k, int l, int colour,
+                                              int m, WAt&& wat, GAt&& gat, double& acc_b, double& acc_r)
+{
+    const Layout& L = a.L;
+    const int64_t s1 = 1, s2 = L.p1, s3 = (int64_t)L.p1 * L.p2, s4 = s3 * L.p3;
+    const int64_t sd[4] = {s1, s2, s3, s4};
+    const int idx[4] = {i, j, k, l};
+    const int nn[4] = {L.n1, L.n2, L.n3, L.n4};
+    // w at p + o, o a sum of at most two signed unit offsets (axis, sign)
+    auto w1 = [&](int d, int sg) {
+        return wat(d == 0 ? sg : 0, d == 1 ? sg : 0, d == 2 ? sg : 0, d == 3 ? sg : 0);
+    };
+    auto w2 = [&](int d, int sd_, int t, int st) {
+        return wat((d == 0 ? sd_ : 0) + (t == 0 ? st : 0), (d == 1 ? sd_ : 0) + (t == 1 ? st : 0),
+                   (d == 2 ? sd_ : 0) + (t == 2 ? st : 0), (d == 3 ? sd_ : 0) + (t == 3 ? st : 0));
+    };
+    const double w0 = wat(0, 0, 0, 0);
+    // face neighbours
+    double wm[4], wp[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) { wm[d] = w1(d, -1); wp[d] = w1(d, 1); }
+    double q[8];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const double gnm = (w0 - wm[d]) * a.inv_h;   // normal, -e_d face
+        const double gnp = (wp[d] - w0) * a.inv_h;   // normal, +e_d face
+        double qm = gnm * gnm, qp = gnp * gnp;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (t == d) continue;
+            const double wpt = wp[t], wmt = wm[t];
+            const double dm_pt = w2(d, -1, t, 1), dm_mt = w2(d, -1, t, -1);
+            const double dp_pt = w2(d, 1, t, 1), dp_mt = w2(d, 1, t, -1);
+            const double tm = ((dm_pt + wpt) - (dm_mt + wmt)) * (0.25 * a.inv_h);
+            const double tp = ((wpt + dp_pt) - (wmt + dp_mt)) * (0.25 * a.inv_h);
+            qm += tm * tm;
+            qp += tp * tp;
+        }
+        q[2 * d] = qm;
+        q[2 * d + 1] = qp;
+    }
+    double qs = 0.0;
+#pragma unroll
+    for (int f = 0; f < 8; ++f) qs += q[f];
+    const double abar = sqrt(a.eps2 + qs / 8.0);
+    const double scale = a.th2 * abar;
+    double c[8];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const double gm = gat(d, 0);     // face -e_d: G_d of p - e_d
+        const double gp = gat(d, 1);     // face +e_d: G_d of p
+        c[2 * d] = scale * gm / sqrt(a.eps2 + q[2 * d]);
+        c[2 * d + 1] = scale * gp / sqrt(a.eps2 + q[2 * d + 1]);
+    }
+    double D = 1.0;
+#pragma unroll
+    for (int f = 0; f < 8; ++f) D += c[f];
+    // right-hand side and residual of the initial iterate: Dirichlet
+    // neighbours take the new level's data
+    double bfull = w0, off = 0.0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const double vm = idx[d] == 1 ? a.ub[p - sd[d]] : wm[d];
+        const double vp = idx[d] == nn[d] ? a.ub[p + sd[d]] : wp[d];
+        off += c[2 * d] * vm + c[2 * d + 1] * vp;
+        if (idx[d] == 1) bfull += c[2 * d] * vm;
+        if (idx[d] == nn[d]) bfull += c[2 * d + 1] * vp;
+    }
+    const double r0 = (w0 + off) - D * w0;
+    acc_b += bfull * bfull;
+    acc_r += r0 * r0;
+    const int64_t irow = ((int64_t)(l - 1) * L.n3 + (k - 1)) * L.n2 + (j - 1);
+    if (MODE == kSplit) {
+        const int64_t ci = ctile(L, colour, irow, m);
+#pragma unroll
+        for (int f = 0; f < 8; ++f) a.coef[ci + f * kTileSlots] = c[f];
+        a.coef[ci + 8 * kTileSlots] = w0;
+        if (a.coef16) {
+            const double inv = 1.0 / D;
+            uint32_t h[8];
+#pragma unroll
+            for (int f = 0; f < 8; ++f) h[f] = bf16_bits((float)(c[f] * inv));
+            a.coef16[mrec(L, colour, irow, m)] =
+                make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+        }
+    } else {
+        const int64_t qi = irow * L.n1 + (i - 1);
+#pragma unroll
+        for (int f = 0; f < 8; ++f) a.coef_nat[qi * 8 + f] = c[f];
+        a.b_nat[qi] = bfull;
+    }
+}
+
+// One thread per padded cell (flat order): ghost cells only copy the new
+// level's Dirichlet value into the colour-split u; interior cells assemble.
+// Used for the natural-layout export.
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
 {
     __shared__ double lds[4];
     __shared__ int flag;
     const Layout& L = a.L;
-    const int64_t s1 = 1, s2 = L.p1, s3 = (int64_t)L.p1 * L.p2, s4 = s3 * L.p3;
-    const int64_t sd[4] = {s1, s2, s3, s4};
     double acc_b = 0.0, acc_r = 0.0;
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < L.npad; p += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(p % L.p1);
@@ -63,101 +185,154 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
             else a.ublack[us] = v0;
         }
         if (!inside) continue;
-        const int idx[4] = {i, j, k, l};
-        const int nn[4] = {L.n1, L.n2, L.n3, L.n4};
-        // face neighbours
-        double wm[4], wp[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) { wm[d] = a.w[p - sd[d]]; wp[d] = a.w[p + sd[d]]; }
-        double q[8];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            const double gnm = (w0 - wm[d]) * a.inv_h;   // normal, -e_d face
-            const double gnp = (wp[d] - w0) * a.inv_h;   // normal, +e_d face
-            double qm = gnm * gnm, qp = gnp * gnp;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                if (t == d) continue;
-                const double wpt = a.w[p + sd[t]], wmt = a.w[p - sd[t]];
-                const double dm_pt = a.w[p - sd[d] + sd[t]], dm_mt = a.w[p - sd[d] - sd[t]];
-                const double dp_pt = a.w[p + sd[d] + sd[t]], dp_mt = a.w[p + sd[d] - sd[t]];
-                const double tm = ((dm_pt + wpt) - (dm_mt + wmt)) * (0.25 * a.inv_h);
-                const double tp = ((wpt + dp_pt) - (wmt + dp_mt)) * (0.25 * a.inv_h);
-                qm += tm * tm;
-                qp += tp * tp;
-            }
-            q[2 * d] = qm;
-            q[2 * d + 1] = qp;
-        }
-        double qs = 0.0;
-#pragma unroll
-        for (int f = 0; f < 8; ++f) qs += q[f];
-        const double abar = sqrt(a.eps2 + qs / 8.0);
-        const double scale = a.th2 * abar;
-        double c[8];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            const double gm = a.G[(int64_t)d * L.npad + p - sd[d]];
-            const double gp = a.G[(int64_t)d * L.npad + p];
-            c[2 * d] = scale * gm / sqrt(a.eps2 + q[2 * d]);
-            c[2 * d + 1] = scale * gp / sqrt(a.eps2 + q[2 * d + 1]);
-        }
-        double D = 1.0;
-#pragma unroll
-        for (int f = 0; f < 8; ++f) D += c[f];
-        // right-hand side and residual of the initial iterate: Dirichlet
-        // neighbours take the new level's data
-        double bfull = w0, off = 0.0;
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            const double vm = idx[d] == 1 ? a.ub[p - sd[d]] : wm[d];
-            const double vp = idx[d] == nn[d] ? a.ub[p + sd[d]] : wp[d];
-            off += c[2 * d] * vm + c[2 * d + 1] * vp;
-            if (idx[d] == 1) bfull += c[2 * d] * vm;
-            if (idx[d] == nn[d]) bfull += c[2 * d + 1] * vp;
-        }
-        const double r0 = (w0 + off) - D * w0;
-        acc_b += bfull * bfull;
-        acc_r += r0 * r0;
-        const int64_t irow = ((int64_t)(l - 1) * L.n3 + (k - 1)) * L.n2 + (j - 1);
-        if (MODE == kSplit) {
-            const int64_t ci = ctile(L, colour, irow, m);
-#pragma unroll
-            for (int f = 0; f < 8; ++f) a.coef[ci + f * kTileSlots] = c[f];
-            a.coef[ci + 8 * kTileSlots] = w0;
-            if (a.coef16) {
-                const double inv = 1.0 / D;
-                uint32_t h[8];
-#pragma unroll
-                for (int f = 0; f < 8; ++f) h[f] = bf16_bits((float)(c[f] * inv));
-                a.coef16[mrec(L, colour, irow, m)] =
-                    make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
-            }
-        } else {
-            const int64_t qi = irow * L.n1 + (i - 1);
-#pragma unroll
-            for (int f = 0; f < 8; ++f) a.coef_nat[qi * 8 + f] = c[f];
-            a.b_nat[qi] = bfull;
-        }
+        const int64_t s2 = L.p1, s3 = (int64_t)L.p1 * L.p2, s4 = s3 * L.p3;
+        const int64_t sd[4] = {1, s2, s3, s4};
+        assemble_cell<MODE>(
+            a, p, i, j, k, l, colour, m,
+            [&](int di, int dj, int dk, int dl) { return a.w[p + di + dj * s2 + dk * s3 + dl * s4]; },
+            [&](int d, int plus) { return a.G[(int64_t)d * L.npad + p - (plus ? 0 : sd[d])]; }, acc_b, acc_r);
     }
     if (MODE != kSplit) return;
-    const double bb = block_sum(acc_b, lds);
-    const double rr = block_sum(acc_r, lds);
-    if (threadIdx.x == 0) { a.part_a[blockIdx.x] = bb; a.part_b[blockIdx.x] = rr; }
-    if (!arrive_last(&a.C->arrive[0], gridDim.x, &flag)) return;
-    const double B2 = sum_partials(a.part_a, gridDim.x, lds);
-    const double R2 = sum_partials(a.part_b, gridDim.x, lds);
-    if (threadIdx.x == 0) {
-        Ctrl* C = a.C;
-        C->bn = sqrt(B2);
-        const double R = sqrt(R2);
-        C->rel_res = C->bn > 0.0 ? R / C->bn : R;
-        C->iterations = 0;
-        C->final_red = 0;
-        if (!(R2 < INFINITY) || !(B2 < INFINITY)) { C->status = SUBSURF4D_ENONFINITE; C->done = 1; }
-        else if (R <= C->tol * C->bn) C->done = 1;
-        else if (C->max_iter <= 0) { C->status = SUBSURF4D_NOT_CONVERGED; C->done = 1; }
-        C->arrive[0] = 0;
+    assembly_decide(a, acc_b, acc_r, lds, &flag);
+}
+
+// Assembly for the solver, frame-marching with the 33-point neighbourhood
+// staged in LDS: a block owns a column tile of 64 interior x-cells x 4
+// y-rows at one z and walks the frames l = 1..N4.  Per frame it loads the
+// 3 planes (z-1, z, z+1) x 6 rows (y-1 .. y+4) x 66 x-cells of frame l+1
+// into a ring of three frame slots, so every w value comes from LDS and each
+// frame's slab is read from memory once per block.  The t-face G of the frame
+// below is kept in a register from the previous frame.  Tiles of one XCD are
+// consecutive (x-tile fastest, then z), so the neighbour planes a block loads
+// are loaded by the blocks beside it at about the same time (L2 hits).  Ghost
+// cells are written by k_ghost_split.
+constexpr int kAx = 66, kAy = 6, kAz = 3;                  // slab: x with halo, y rows with halo, z planes
+constexpr int kSlab = kAx * kAy * kAz;                     // doubles per frame slot
+
+template <bool PREFETCH>
+__global__ __launch_bounds__(kBlock) void k_assemble_cols(AsmArgs a)
+{
+    __shared__ double lds[4];
+    __shared__ int flag;
+    __shared__ double slab[3][kSlab];
+    const Layout& L = a.L;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int nxt = (L.n1 + 63) >> 6;
+    const int njb = (L.n2 + 3) >> 2;
+    const int64_t ncol = (int64_t)nxt * njb * L.n3;
+    const int64_t s2 = L.p1, s3 = (int64_t)L.p1 * L.p2, s4 = s3 * L.p3;
+    double acc_b = 0.0, acc_r = 0.0;
+    for (TileWalk tw(ncol); tw.t < tw.end; tw.t += tw.step) {
+        const int xt = (int)(tw.t % nxt);
+        const int64_t t2 = tw.t / nxt;
+        const int k = (int)(t2 % L.n3) + 1;
+        const int jb = (int)(t2 / L.n3);
+        const int x0 = xt * 64 + 1, j0 = jb * 4 + 1;
+        const int i = x0 + tx;
+        const int j = j0 + ty;
+        const bool active = i <= L.n1 && j <= L.n2;
+        // slab of frame lf: padded x0-1 .. x0+64, y j0-1 .. j0+4, z k-1 .. k+1; this
+        // thread's share (entries threadIdx.x + r*kBlock) goes to registers
+        // first, so the loads of frame l+2 are in flight while frame l is
+        // assembled, and then to the ring slot lf % 3
+        constexpr int kPer = (kSlab + kBlock - 1) / kBlock;
+        double pf[kPer];
+        auto source = [&](int q) -> int64_t {     // offset within a frame, -1: outside the padded box
+            const int pz = q / (kAx * kAy);
+            const int rem = q - pz * (kAx * kAy);
+            const int ry = rem / kAx;
+            const int cx = rem - ry * kAx;
+            const int ii = x0 - 1 + cx, jj = j0 - 1 + ry, kk = k - 1 + pz;
+            return (q < kSlab && ii < L.p1 && jj < L.p2) ? (int64_t)kk * s3 + (int64_t)jj * s2 + ii : -1;
+        };
+        auto fetch = [&](int lf) {
+            const double* fw = a.w + (int64_t)lf * s4;
+#pragma unroll
+            for (int r = 0; r < kPer; ++r) {
+                const int64_t o = source(threadIdx.x + r * kBlock);
+                pf[r] = o >= 0 ? fw[o] : 0.0;
+            }
+        };
+        auto store = [&](int lf) {
+            double* dst = slab[lf % 3];
+#pragma unroll
+            for (int r = 0; r < kPer; ++r) {
+                const int q = threadIdx.x + r * kBlock;
+                if (q < kSlab) dst[q] = pf[r];
+            }
+        };
+        auto load = [&](int lf) {               // without prefetch: straight from memory to LDS
+            double* dst = slab[lf % 3];
+            const double* fw = a.w + (int64_t)lf * s4;
+            for (int q = threadIdx.x; q < kSlab; q += kBlock) {
+                const int64_t o = source(q);
+                dst[q] = o >= 0 ? fw[o] : 0.0;
+            }
+        };
+        __syncthreads();                 // the previous tile's last frame is no longer read
+        load(0);
+        load(1);
+        if (PREFETCH) fetch(2);
+        double gt_below = active ? a.G[3 * L.npad + ((int64_t)k * L.p2 + j) * L.p1 + i] : 0.0;   // G_t of frame 0
+        for (int l = 1; l <= L.n4; ++l) {
+            if (PREFETCH) store(l + 1);
+            else load(l + 1);
+            __syncthreads();
+            if (PREFETCH && l + 2 <= L.n4 + 1) fetch(l + 2);
+            if (active) {
+                const int64_t prow = ((int64_t)l * L.p3 + k) * L.p2 + j;
+                const int64_t p = prow * L.p1 + i;
+                const int colour = (i + j + k + l) & 1;
+                const int m = (i - 1) >> 1;
+                const double w0 = slab[l % 3][(1 * kAy + ty + 1) * kAx + tx + 1];
+                const int64_t us = prow * L.rs + L.xoff + m;
+                if (colour == 0) { a.ured0[us] = w0; a.ured1[us] = w0; }
+                else a.ublack[us] = w0;
+                const double gt_here = a.G[3 * L.npad + p];
+                const int sl[3] = {(l + 2) % 3, l % 3, (l + 1) % 3};      // slots of frames l-1, l, l+1
+                assemble_cell<kSplit>(
+                    a, p, i, j, k, l, colour, m,
+                    [&](int di, int dj, int dk, int dl) {
+                        return slab[sl[dl + 1]][((dk + 1) * kAy + ty + 1 + dj) * kAx + tx + 1 + di];
+                    },
+                    [&](int d, int plus) {
+                        if (d == 3) return plus ? gt_here : gt_below;
+                        const int64_t o = d == 0 ? 1 : (d == 1 ? s2 : s3);
+                        return a.G[(int64_t)d * L.npad + p - (plus ? 0 : o)];
+                    },
+                    acc_b, acc_r);
+                gt_below = gt_here;
+            }
+            __syncthreads();             // frame l-1's slot is refilled with frame l+2 next
+        }
+    }
+    assembly_decide(a, acc_b, acc_r, lds, &flag);
+}
+
+// The ghost layer of the colour-split u: the new level's Dirichlet data.  One
+// wave per padded row: rows in the ghost layer copy every cell, interior rows
+// their two x-ghosts.
+__global__ __launch_bounds__(kBlock) void k_ghost_split(Layout L, const double* __restrict__ ub, double* ured0,
+                                                        double* ured1, double* ublack)
+{
+    const int tx = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t prow = wave; prow < L.nrow_pad; prow += nwaves) {
+        const int j = (int)(prow % L.p2);
+        const int64_t t2 = prow / L.p2;
+        const int k = (int)(t2 % L.p3);
+        const int l = (int)(t2 / L.p3);
+        const bool ghost_row = j == 0 || j > L.n2 || k == 0 || k > L.n3 || l == 0 || l > L.n4;
+        const int step = ghost_row ? 64 : L.p1;
+        for (int i = ghost_row ? tx : (tx == 0 ? 0 : (tx == 1 ? L.n1 + 1 : L.p1)); i < L.p1; i += step) {
+            const int64_t p = prow * L.p1 + i;
+            const int m = (i - 1) >> 1;
+            const int64_t us = prow * L.rs + L.xoff + m;
+            const double v = ub[p];
+            if (((i + j + k + l) & 1) == 0) { ured0[us] = v; ured1[us] = v; }
+            else ublack[us] = v;
+        }
     }
 }
 
@@ -554,6 +729,22 @@ __global__ __launch_bounds__(kBlock) void k_copy_probe(const double2* __restrict
         dst[q] = src[q];
 }
 
+// Read-dominated probe: dst = sum of `reads` source chunks of n 16-byte
+// elements each (reads streams in, one out, as the sweeps' traffic mix).
+__global__ __launch_bounds__(kBlock) void k_stream_probe(const double2* __restrict__ src, double2* __restrict__ dst,
+                                                         int64_t n, int reads)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        double2 acc = src[q];
+        for (int r = 1; r < reads; ++r) {
+            const double2 v = src[(int64_t)r * n + q];
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        dst[q] = acc;
+    }
+}
+
 // colour-split u -> interior of the padded u
 __global__ __launch_bounds__(kBlock) void k_unsplit(Layout L, const double* ured0, const double* ured1,
                                                     const double* ublack, const Ctrl* C, double* u)
@@ -585,6 +776,19 @@ __global__ __launch_bounds__(kBlock) void k_copy_ghosts(Layout L, const double* 
         const int l = (int)(t2 / L.p3);
         const bool inside = i >= 1 && i <= L.n1 && j >= 1 && j <= L.n2 && k >= 1 && k <= L.n3 && l >= 1 && l <= L.n4;
         if (!inside) u[p] = ub[p];
+    }
+}
+
+// Outcome of the solve into a device-accessible result (enqueue-only calls).
+__global__ void k_write_result(const Ctrl* C, subsurf4d_result* res, int sweeps_per_pass)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        res->status = C->status;
+        res->iterations = sweeps_per_pass > 0 ? C->outer * sweeps_per_pass : C->iterations;
+        res->outer_iterations = C->outer;
+        res->reserved = 0;
+        res->rel_residual = C->rel_res;
+        res->bnorm = C->bn;
     }
 }
 
@@ -675,6 +879,31 @@ int run_sor_loop(const WsPlan& P, const subsurf4d_step_params& sp, void* ws, hip
     black.uin = black.uout = ublack;
     red.uoth = ublack;
 
+    // red half-sweep k (which also tests iterate k-1) and black half-sweep k;
+    // every launch returns at once after the stopping rule has been met
+    auto enqueue_iteration = [&](int k) {
+        red.k = k;
+        red.uin = ured[(k - 1) & 1];
+        red.uout = ured[k & 1];
+        red.check = (k >= 2) && (((k - 1) % check_every == 0) || (k - 1 >= max_iter));
+        if (variant == 2) k_sweep_t2<0><<<grid, kBlock, 0, s>>>(red);
+        else if (variant == 1) k_sweep_tm<0><<<grid, kBlock, 0, s>>>(red);
+        else k_sweep<0><<<grid, kBlock, 0, s>>>(red);
+        if (k <= max_iter) {
+            black.k = k;
+            black.uoth = ured[k & 1];
+            if (variant == 2) k_sweep_t2<1><<<grid, kBlock, 0, s>>>(black);
+            else if (variant == 1) k_sweep_tm<1><<<grid, kBlock, 0, s>>>(black);
+            else k_sweep<1><<<grid, kBlock, 0, s>>>(black);
+        }
+    };
+    if (sp.flags & SUBSURF4D_FLAG_ASYNC) {
+        // enqueue-only: every iteration up to the cap, no host read
+        for (int k = 1; k <= max_iter + 1; ++k) enqueue_iteration(k);
+        SS4_LAUNCHED("sweeps");
+        return 0;
+    }
+
     Ctrl hc;
     SS4_HIP(hipMemcpyAsync(&hc, C, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     SS4_HIP(hipStreamSynchronize(s));
@@ -683,22 +912,7 @@ int run_sor_loop(const WsPlan& P, const subsurf4d_step_params& sp, void* ws, hip
     int chunk = sp.iter_hint > 0 ? sp.iter_hint + 1 : 8;
     while (!hc.done) {
         timer.begin();
-        for (int c = 0; c < chunk && k <= max_iter + 1; ++c, ++k) {
-            red.k = k;
-            red.uin = ured[(k - 1) & 1];
-            red.uout = ured[k & 1];
-            red.check = (k >= 2) && (((k - 1) % check_every == 0) || (k - 1 >= max_iter));
-            if (variant == 2) k_sweep_t2<0><<<grid, kBlock, 0, s>>>(red);
-            else if (variant == 1) k_sweep_tm<0><<<grid, kBlock, 0, s>>>(red);
-            else k_sweep<0><<<grid, kBlock, 0, s>>>(red);
-            if (k <= max_iter) {
-                black.k = k;
-                black.uoth = ured[k & 1];
-                if (variant == 2) k_sweep_t2<1><<<grid, kBlock, 0, s>>>(black);
-                else if (variant == 1) k_sweep_tm<1><<<grid, kBlock, 0, s>>>(black);
-                else k_sweep<1><<<grid, kBlock, 0, s>>>(black);
-            }
-        }
+        for (int c = 0; c < chunk && k <= max_iter + 1; ++c, ++k) enqueue_iteration(k);
         SS4_LAUNCHED("sweeps");
         timer.end();
         SS4_HIP(hipMemcpyAsync(&hc, C, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
@@ -740,6 +954,29 @@ int run_copy_probe(const void* src, void* dst, size_t bytes, int reps, double* m
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     SS4_LAUNCHED("copy probe");
+    return 0;
+}
+
+int run_stream_probe(const void* src, void* dst, size_t bytes, int reads, int reps, double* ms, hipStream_t s)
+{
+    const int64_t n = (int64_t)(bytes / 16);
+    hipEvent_t a, b;
+    SS4_HIP(hipEventCreate(&a));
+    SS4_HIP(hipEventCreate(&b));
+    const int grid = 8192;
+    const double2* sp = static_cast<const double2*>(src);
+    double2* dp = static_cast<double2*>(dst);
+    k_stream_probe<<<grid, kBlock, 0, s>>>(sp, dp, n, reads);
+    SS4_HIP(hipEventRecord(a, s));
+    for (int r = 0; r < reps; ++r) k_stream_probe<<<grid, kBlock, 0, s>>>(sp, dp, n, reads);
+    SS4_HIP(hipEventRecord(b, s));
+    SS4_HIP(hipEventSynchronize(b));
+    float t = 0.f;
+    SS4_HIP(hipEventElapsedTime(&t, a, b));
+    *ms = (double)t / reps;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    SS4_LAUNCHED("stream probe");
     return 0;
 }
 
@@ -789,7 +1026,22 @@ int launch_assembly(const WsPlan& P, double h, const double* G, const double* w,
     a.part_a = ws_ptr<double>(ws, P.part_a);
     a.part_b = ws_ptr<double>(ws, P.part_b);
     a.C = ws_ptr<Ctrl>(ws, P.ctrl);
-    k_assemble<kSplit><<<grid_for(P.L.npad), kBlock, 0, s>>>(a);
+    const Layout& L = P.L;
+    k_ghost_split<<<grid_for(L.nrow_pad * 64), kBlock, 0, s>>>(L, a.ub, a.ured0, a.ured1, a.ublack);
+    const int64_t ncol = (int64_t)((L.n1 + 63) >> 6) * ((L.n2 + 3) >> 2) * L.n3;
+    // SUBSURF4D_ASM_PREFETCH=0|1 selects the slab loading: loads of the next
+    // frame issued after the barrier and kept in flight during the cell
+    // arithmetic (1), or issued just before the frame's LDS store (0); both
+    // give the same bits
+    static const char* env = getenv("SUBSURF4D_ASM_PREFETCH");
+    const bool prefetch = !(env && env[0] == '0');
+    const void* kern = prefetch ? reinterpret_cast<const void*>(&k_assemble_cols<true>)
+                                : reinterpret_cast<const void*>(&k_assemble_cols<false>);
+    const int res = resident_grid(kern);
+    const int64_t g = ncol < res ? ncol : res;
+    const int grid = (int)((g + kXcd - 1) / kXcd * kXcd);
+    if (prefetch) k_assemble_cols<true><<<grid, kBlock, 0, s>>>(a);
+    else k_assemble_cols<false><<<grid, kBlock, 0, s>>>(a);
     SS4_LAUNCHED("assemble");
     return 0;
 }
@@ -827,6 +1079,13 @@ int run_step(const WsPlan& P, double h, const double* G, const double* ub, const
         const int r2 = run_rescale(P, centres, nc, sp.ball_r, owner, u, ws, s);
         if (r2 < 0) return r2;
     }
+    if (sp.flags & SUBSURF4D_FLAG_ASYNC) {
+        if (res) {
+            k_write_result<<<1, 64, 0, s>>>(C, res, sp.precision == SUBSURF4D_MIXED ? sp.inner_sweeps : 0);
+            SS4_LAUNCHED("result");
+        }
+        return 0;
+    }
     SS4_HIP(hipStreamSynchronize(s));
     return res ? res->status : 0;
 }
@@ -849,6 +1108,13 @@ int run_solve(const WsPlan& P, const double* coef, const double* b, double* u,
     if (rc < 0) return rc;
     rc = run_unsplit(P, u, ws, s);
     if (rc < 0) return rc;
+    if (sp.flags & SUBSURF4D_FLAG_ASYNC) {
+        if (res) {
+            k_write_result<<<1, 64, 0, s>>>(C, res, 0);
+            SS4_LAUNCHED("result");
+        }
+        return 0;
+    }
     SS4_HIP(hipStreamSynchronize(s));
     return res ? res->status : 0;
 }

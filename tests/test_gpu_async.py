@@ -1,0 +1,108 @@
+"""Enqueue-only calls (SUBSURF4D_FLAG_ASYNC): no host synchronisation, the
+outcome written to device memory, and the whole step capturable in a HIP
+graph.  The eager enqueue-only step gives the bits of the synchronising step
+(same kernels, same iterate); a captured config-1 FP64 step, replayed several
+times with other work and synchronisations between the replays, matches the
+red-black oracle at 1e-10 on every replay."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+import oracle as orc  # noqa: E402
+import synth  # noqa: E402
+from paper_2111_11866_amd import binding as B  # noqa: E402
+
+DEV = "cuda"
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    img = synth.spheres_cfg1()
+    prep = orc.prepare(img.n, img.image, img.centres, orc.PrepareParams())
+    w = orc.rescale(img.n, orc.init_u(img.n, img.seeds, 1.0, 0.0), img.centres, 8.0, prep["owner"])
+    cen, nc = B.centres_tensor(img.centres)
+    return dict(img=img, prep=prep, w=w, G=T(prep["G"]), owner=T(prep["owner"]), cen=cen, nc=nc)
+
+
+@pytest.mark.parametrize("precision", [B.FP64, B.MIXED])
+def test_async_step_equals_sync_step(cfg1, precision):
+    n = cfg1["img"].n
+    ws = B.alloc_workspace(n, cfg1["nc"], precision)
+    sp = B.StepParams(precision=precision, max_iter=400, inner_sweeps=8, refine_tol=1e-10)
+    u_sync = T(cfg1["w"])
+    r_sync = B.step(n, 1.0, cfg1["G"], cfg1["cen"], cfg1["nc"], cfg1["owner"], u_sync, sp, ws)
+    u = T(cfg1["w"])
+    res = B.result_tensor()
+    B.step_async(n, 1.0, cfg1["G"], cfg1["cen"], cfg1["nc"], cfg1["owner"], u, sp, ws, res)
+    r = B.result_dict(res)          # synchronises
+    assert r == r_sync
+    assert torch.equal(u, u_sync)
+
+
+def test_async_not_converged_and_solve(cfg1):
+    """The cap of an enqueue-only call bounds its launches: at max_iter the
+    result says NOT_CONVERGED with the capped iterate, as the synchronising
+    call; the solve alone behaves the same."""
+    n = (9, 8, 7, 3)
+    rng = np.random.default_rng(3)
+    G = rng.uniform(0.05, 1, size=(4,) + B.padded_shape(n))
+    w = np.zeros(B.padded_shape(n))
+    w[1:-1, 1:-1, 1:-1, 1:-1] = rng.uniform(0, 1, size=B.interior_shape(n))
+    coef, b = orc.assemble(n, G, w, 1.0, 1e-2, 0.5)
+    ws = B.alloc_workspace(n)
+    sp = B.StepParams(tol=1e-14, max_iter=3, rescale=False)
+    res = B.result_tensor()
+    u = T(w)
+    B.solve_async(n, 1.0, T(coef), T(b), u, sp, ws, res)
+    r = B.result_dict(res)
+    ref, it, rr, st = orc.sor(n, coef, b, w, sp.omega, 0.0, 3, orc.RB)
+    assert r["status"] == B.NOT_CONVERGED and r["iterations"] == 3
+    assert np.abs(u.cpu().numpy() - ref)[1:-1, 1:-1, 1:-1, 1:-1].max() <= 1e-12
+    u = T(w)
+    B.step_async(n, 1.0, T(G), None, 0, None, u, replace(sp, tol=1e-9, max_iter=400), ws, res)
+    r = B.result_dict(res)
+    u2 = T(w)
+    r2 = B.step(n, 1.0, T(G), None, 0, None, u2, replace(sp, tol=1e-9, max_iter=400), ws)
+    assert r == r2 and r["status"] == 0 and torch.equal(u, u2)
+
+
+def test_graph_captured_step_cfg1(cfg1):
+    img, prep = cfg1["img"], cfg1["prep"]
+    n = img.n
+    ws = B.alloc_workspace(n, cfg1["nc"])
+    sp = B.StepParams(max_iter=120)
+    ref = orc.step(n, prep["G"], cfg1["w"], img.centres, prep["owner"], orc.StepParams(), orc.RB)
+    u = T(cfg1["w"])
+    res = B.result_tensor()
+    # eager warm-up on the capture's buffers, then capture one whole step
+    B.step_async(n, 1.0, cfg1["G"], cfg1["cen"], cfg1["nc"], cfg1["owner"], u, sp, ws, res)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        B.step_async(n, 1.0, cfg1["G"], cfg1["cen"], cfg1["nc"], cfg1["owner"], u, sp, ws, res)
+    w0 = T(cfg1["w"])
+    other = T(cfg1["w"])
+    ows = B.alloc_workspace(n, cfg1["nc"])
+    for rep in range(3):
+        u.copy_(w0)
+        res.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        r = B.result_dict(res)
+        assert r["status"] == 0 and r["iterations"] == ref["iterations"], (rep, r, ref["iterations"])
+        err = float(np.abs(u.cpu().numpy() - ref["u_resc"]).max())
+        assert err <= 1e-10, (rep, err)
+        # the program's own eager work between replays
+        other.copy_(w0)
+        B.step(n, 1.0, cfg1["G"], cfg1["cen"], cfg1["nc"], cfg1["owner"], other, B.StepParams(), ows)
+        torch.cuda.synchronize()

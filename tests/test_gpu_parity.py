@@ -502,3 +502,66 @@ def test_deterministic_repeat(cfg1):
     a, ra = step_gpu(n, T(cfg1["prep"]["G"]), cfg1["w0"], cen, nc, T(cfg1["prep"]["owner"]), sp, ws)
     b, rb = step_gpu(n, T(cfg1["prep"]["G"]), cfg1["w0"], cen, nc, T(cfg1["prep"]["owner"]), sp, ws)
     assert np.array_equal(a, b) and ra == rb
+
+
+def test_stream_probe_sums_chunks():
+    """The read-dominated bandwidth probe computes dst = sum of its source chunks."""
+    n = 1 << 16
+    src = torch.arange(3 * 2 * n, dtype=torch.float64, device=DEV)
+    dst = torch.empty(2 * n, dtype=torch.float64, device=DEV)
+    ms = B.stream_probe(src, dst, 3, reps=2)
+    assert ms > 0.0
+    want = src.view(3, 2 * n).sum(0)
+    assert torch.equal(dst, want)
+
+
+def test_red_phase_reads_only_black():
+    """Red-black ordering (Sec. 3.2.2): the red half-sweep reads only black
+    neighbours.  With omega = 1 one iteration's result does not depend on the
+    red values of the initial guess: poisoning them (1e100) leaves the iterate,
+    its iteration count and its residual bitwise unchanged, while poisoning
+    the black values changes the result."""
+    n = (33, 9, 7, 3)
+    G, w, coef, b = random_system(n, 99)
+    idx = np.indices(B.padded_shape(n)).sum(0)          # l + k + j + i
+    interior = np.zeros(B.padded_shape(n), dtype=bool)
+    interior[1:-1, 1:-1, 1:-1, 1:-1] = True
+    red = interior & (idx % 2 == 0)
+    sp = B.StepParams(omega=1.0, fixed_iters=1, rescale=False)
+    ws = B.alloc_workspace(n)
+    u0 = w.copy(); u0[red] = 0.0
+    a = T(u0)
+    ra = B.solve(n, 1.0, T(coef), T(b), a, sp, ws)
+    up = w.copy(); up[red] = 1e100
+    p = T(up)
+    rp = B.solve(n, 1.0, T(coef), T(b), p, sp, ws)
+    assert np.array_equal(H(a)[interior], H(p)[interior]) and ra["iterations"] == rp["iterations"] == 1
+    assert ra["rel_res"] == rp["rel_res"]
+    ub = u0.copy(); ub[interior & ~red] = 1e100
+    q = T(ub)
+    B.solve(n, 1.0, T(coef), T(b), q, sp, ws)
+    assert not np.array_equal(H(q)[interior], H(a)[interior])
+
+
+def test_checkpoint_resume_bit_identical(cfg1, tmp_path):
+    """20 steps in one go equal 10 steps, a checkpoint to disk, a fresh job
+    resumed from it, and 10 more steps, bitwise."""
+    img, sp = cfg1["img"], cfg1["sp"]
+    full = B.Job(img.n, img.image, img.centres, img.seeds)
+    assert full.prepare(cfg1["pp"]) == 0
+    full.init(v=1.0, R=0.0, ball_r=sp.ball_r)
+    for _ in range(20):
+        full.step(sp)
+    half = B.Job(img.n, img.image, img.centres, img.seeds)
+    half.prepare(cfg1["pp"])
+    half.init(v=1.0, R=0.0, ball_r=sp.ball_r)
+    for _ in range(10):
+        half.step(sp)
+    path = str(tmp_path / "job.npz")
+    half.save(path)
+    del half
+    resumed = B.Job(img.n, img.image, img.centres, img.seeds)
+    resumed.load(path)
+    for _ in range(10):
+        resumed.step(sp)
+    assert torch.equal(resumed.u, full.u)
