@@ -58,7 +58,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("paper_2111_11866_amd/csrc/ss4_solve.hip", "paper_2111_11866_amd/csrc/ss4_common.hpp")
+KERNEL_SOURCES = ("paper_2111_11866_amd/csrc/ss4_sweep.hpp", "paper_2111_11866_amd/csrc/ss4_common.hpp")
 COUNTER_SUMMARY = "profiles/k_sweep_config2_counters.md"
 
 
@@ -469,6 +469,22 @@ def main():
         "preparation_note": "owner map, local thresholds, two presmoothing heat solves and face G of the whole volume; "
                             "once per job, outside the timed steps",
     }
+    # cell tracking (Sec. 5) on the segmentation after the timed steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cells, lab, d2 = B.track(n, job.u, 0.5, capacity=1 << 20, join_radius=3.0)
+    torch.cuda.synchronize()
+    t_track = time.perf_counter() - t0
+    kinds = np.bincount(cells["kind"], minlength=4) if len(cells) else np.zeros(4, int)
+    out["tracking"] = {"ms": t_track * 1e3, "cells": int(len(cells)),
+                       "cells_per_frame_mean": float(len(cells)) / n[3],
+                       "links": {"none": int(kinds[0]), "centre": int(kinds[1]), "overlap": int(kinds[2]),
+                                 "joined": int(kinds[3])},
+                       "note": "u >= 0.5 after the timed steps; labels, distances, centres, backward links on the GPU, "
+                               "joining (radius 3 voxels) on the host; includes the copy of the cell records"}
+    log(f"[bench] tracking: {len(cells)} cells in {t_track * 1e3:.1f} ms, links {kinds.tolist()}")
+    del lab, d2
+    torch.cuda.empty_cache()
     ct = counter_traffic()
     if ct is not None:
         out["roofline"]["traffic"] = ct["hbm_bytes_per_launch"]
@@ -555,6 +571,20 @@ def main():
     out["copy_probe"] = {"bytes_moved": 2 * nb, "ms": ms, "GBs": 2 * nb / (ms * 1e-3) / 1e9,
                          "frac_of_peak": 2 * nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     del src, dst
+    # read-dominated probes: k streams of 1 GiB summed into one (k = 2: the
+    # STREAM triad's mix; k = 11: about the FP64 sweep's 11 reads per write)
+    chunk = 1 << 30
+    out["stream_probe"] = {}
+    for k in (2, 11):
+        src = torch.ones(k * chunk // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty(chunk // 8, dtype=torch.float64, device="cuda")
+        ms = B.stream_probe(src, dst, k, reps=5)
+        moved = (k + 1) * chunk
+        out["stream_probe"][f"reads_{k}_per_write"] = {"bytes_moved": moved, "ms": ms,
+                                                        "GBs": moved / (ms * 1e-3) / 1e9,
+                                                        "frac_of_peak": moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        del src, dst
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(img, sp, args.cpu_seconds)
