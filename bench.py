@@ -472,18 +472,18 @@ def main():
     # cell tracking (Sec. 5) on the segmentation after the timed steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    cells, lab, d2 = B.track(n, job.u, 0.5, capacity=1 << 20, join_radius=3.0)
+    tcells, lab, d2 = B.track(n, job.u, 0.5, capacity=1 << 20, join_radius=3.0)
     torch.cuda.synchronize()
     t_track = time.perf_counter() - t0
-    kinds = np.bincount(cells["kind"], minlength=4) if len(cells) else np.zeros(4, int)
-    out["tracking"] = {"ms": t_track * 1e3, "cells": int(len(cells)),
-                       "cells_per_frame_mean": float(len(cells)) / n[3],
+    kinds = np.bincount(tcells["kind"], minlength=4) if len(tcells) else np.zeros(4, int)
+    out["tracking"] = {"ms": t_track * 1e3, "cells": int(len(tcells)),
+                       "cells_per_frame_mean": float(len(tcells)) / n[3],
                        "links": {"none": int(kinds[0]), "centre": int(kinds[1]), "overlap": int(kinds[2]),
                                  "joined": int(kinds[3])},
                        "note": "u >= 0.5 after the timed steps; labels, distances, centres, backward links on the GPU, "
                                "joining (radius 3 voxels) on the host; includes the copy of the cell records"}
-    log(f"[bench] tracking: {len(cells)} cells in {t_track * 1e3:.1f} ms, links {kinds.tolist()}")
-    del lab, d2
+    log(f"[bench] tracking: {len(tcells)} cells in {t_track * 1e3:.1f} ms, links {kinds.tolist()}")
+    del lab, d2, tcells
     torch.cuda.empty_cache()
     ct = counter_traffic()
     if ct is not None:

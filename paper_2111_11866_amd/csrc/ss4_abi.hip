@@ -37,7 +37,9 @@ void timing_add(double ms, int64_t launches, int64_t updates)
     g_timing.solves += 1;
 }
 
-int resident_grid(const void* kernel)
+int resident_grid(const void* kernel) { return resident_grid_bs(kernel, kBlock); }
+
+int resident_grid_bs(const void* kernel, int block)
 {
     static std::mutex mu;
     static std::map<std::pair<int, const void*>, int> cache;
@@ -49,7 +51,7 @@ int resident_grid(const void* kernel)
     if (it != cache.end()) return it->second;
     int cus = 0, per = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) != hipSuccess || per <= 0) per = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) != hipSuccess || per <= 0) per = 1;
     int64_t grid = (int64_t)per * cus;
     grid = grid / kXcd * kXcd;
     if (grid < kXcd) grid = kXcd;

@@ -78,8 +78,16 @@ __global__ __launch_bounds__(kBlock) void kb_split_u(BTable T)
     });
 }
 
-// Assembly of every job, one thread per interior cell (no lane of a wave
-// idles on a ghost cell), writing the flat layout.
+// Assembly of every job, frame-marching: a work item is 256 consecutive
+// (i,j,k) positions of one frame, and each thread walks the frames l = 1..N4
+// of its position.  The values of u at the position and its six x/y/z
+// neighbours are kept for frames l-1, l and l+1 in registers (they are the
+// cell's t-neighbours and t-diagonals), so per frame a thread loads the seven
+// of frame l+1 and the twelve in-frame diagonals of frame l; the t-face G of
+// the frame below is kept as well.  Writes the colour-split tiles, the BF16
+// records, r/D of the initial iterate, and one partial of ||b||^2 and of the
+// initial residual per wave and item (a job's partials do not depend on the
+// rest of the batch).
 __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
 {
     for_runs(T.int_start, nullptr, T.n_jobs, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
@@ -92,29 +100,69 @@ __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
         SS4_GLOBAL double* pa = gbl(J.part_a);
         SS4_GLOBAL double* pb = gbl(J.part_b);
         const uint32_t npad = (uint32_t)J.npad;
-        const uint32_t nint = (uint32_t)J.nint;
+        const uint32_t nfr = (uint32_t)J.n1 * (uint32_t)J.n2 * (uint32_t)J.n3;
         const uint32_t sd[4] = {1u, (uint32_t)J.p1, (uint32_t)J.p1 * J.p2, (uint32_t)J.p1 * J.p2 * J.p3};
         const int nn[4] = {J.n1, J.n2, J.n3, J.n4};
         for (uint32_t item = i0; item < i1; item += step) {
             const uint32_t qi = item * kItem + threadIdx.x;
             double acc_b = 0.0, acc_r = 0.0;
-            if (qi < nint) {
+            if (qi < nfr) {
                 const uint32_t r1 = fdiv(qi, J.mg_n1);
                 const int i = (int)(qi - r1 * (uint32_t)J.n1) + 1;
                 const uint32_t r2 = fdiv(r1, J.mg_n2);
                 const int j = (int)(r1 - r2 * (uint32_t)J.n2) + 1;
-                const uint32_t r3 = fdiv(r2, J.mg_n3);
-                const int k = (int)(r2 - r3 * (uint32_t)J.n3) + 1;
-                const int l = (int)r3 + 1;
-                const uint32_t p = (((uint32_t)l * J.p3 + (uint32_t)k) * J.p2 + (uint32_t)j) * J.p1 + (uint32_t)i;
-                const int colour = (i + j + k + l) & 1;
-                const int m = (i - 1) >> 1;
-                const double w0 = u[p];
-                {
+                const int k = (int)r2 + 1;
+                const uint32_t p0 = ((uint32_t)k * J.p2 + (uint32_t)j) * J.p1 + (uint32_t)i;   // frame 0
+                // u at the position and its x/y/z neighbours: 0 itself, 1/2 -x/+x, 3/4 -y/+y, 5/6 -z/+z
+                auto axis = [&](uint32_t q, double (&A)[7]) {
+                    A[0] = u[q];
+                    A[1] = u[q - sd[0]];
+                    A[2] = u[q + sd[0]];
+                    A[3] = u[q - sd[1]];
+                    A[4] = u[q + sd[1]];
+                    A[5] = u[q - sd[2]];
+                    A[6] = u[q + sd[2]];
+                };
+                double Am[7], Ac[7], Ap[7];
+                axis(p0, Am);
+                axis(p0 + sd[3], Ac);
+                double gt_below = G[3u * npad + p0];
+                for (int l = 1; l <= J.n4; ++l) {
+                    const uint32_t p = p0 + (uint32_t)l * sd[3];
+                    axis(p + sd[3], Ap);
+                    double dxy[2][2], dxz[2][2], dyz[2][2];   // in-frame diagonals [-/+][-/+]
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const int sa = 2 * a - 1, sc = 2 * c - 1;
+                            dxy[a][c] = u[p + sa * (int)sd[0] + sc * (int)sd[1]];
+                            dxz[a][c] = u[p + sa * (int)sd[0] + sc * (int)sd[2]];
+                            dyz[a][c] = u[p + sa * (int)sd[1] + sc * (int)sd[2]];
+                        }
+                    // u at p + (dx, dy, dz, dt), at most two offsets non-zero
+                    auto wat = [&](int dx, int dy, int dz, int dt) -> double {
+                        const int ax = dx ? (dx < 0 ? 1 : 2) : dy ? (dy < 0 ? 3 : 4) : dz ? (dz < 0 ? 5 : 6) : 0;
+                        if (dt != 0) return dt < 0 ? Am[ax] : Ap[ax];
+                        if ((dx != 0) + (dy != 0) + (dz != 0) <= 1) return Ac[ax];
+                        if (dz == 0) return dxy[(dx + 1) / 2][(dy + 1) / 2];
+                        if (dy == 0) return dxz[(dx + 1) / 2][(dz + 1) / 2];
+                        return dyz[(dy + 1) / 2][(dz + 1) / 2];
+                    };
+                    auto w1 = [&](int d, int sg) {
+                        return wat(d == 0 ? sg : 0, d == 1 ? sg : 0, d == 2 ? sg : 0, d == 3 ? sg : 0);
+                    };
+                    auto w2 = [&](int d, int sgd, int t, int sgt) {
+                        return wat((d == 0 ? sgd : 0) + (t == 0 ? sgt : 0), (d == 1 ? sgd : 0) + (t == 1 ? sgt : 0),
+                                   (d == 2 ? sgd : 0) + (t == 2 ? sgt : 0), (d == 3 ? sgd : 0) + (t == 3 ? sgt : 0));
+                    };
+                    const int colour = (i + j + k + l) & 1;
+                    const int m = (i - 1) >> 1;
+                    const double w0 = Ac[0];
                     const int idx[4] = {i, j, k, l};
                     double wm[4], wp[4], q[8];
 #pragma unroll
-                    for (int d = 0; d < 4; ++d) { wm[d] = u[p - sd[d]]; wp[d] = u[p + sd[d]]; }
+                    for (int d = 0; d < 4; ++d) { wm[d] = w1(d, -1); wp[d] = w1(d, 1); }
 #pragma unroll
                     for (int d = 0; d < 4; ++d) {
                         const double gnm = (w0 - wm[d]) * J.inv_h;
@@ -124,8 +172,8 @@ __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
                         for (int t = 0; t < 4; ++t) {
                             if (t == d) continue;
                             const double wpt = wp[t], wmt = wm[t];
-                            const double dm_pt = u[p - sd[d] + sd[t]], dm_mt = u[p - sd[d] - sd[t]];
-                            const double dp_pt = u[p + sd[d] + sd[t]], dp_mt = u[p + sd[d] - sd[t]];
+                            const double dm_pt = w2(d, -1, t, 1), dm_mt = w2(d, -1, t, -1);
+                            const double dp_pt = w2(d, 1, t, 1), dp_mt = w2(d, 1, t, -1);
                             const double tm = ((dm_pt + wpt) - (dm_mt + wmt)) * (0.25 * J.inv_h);
                             const double tp = ((wpt + dp_pt) - (wmt + dp_mt)) * (0.25 * J.inv_h);
                             qm += tm * tm;
@@ -138,12 +186,16 @@ __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
 #pragma unroll
                     for (int f = 0; f < 8; ++f) qs += q[f];
                     const double scale = J.th2 * sqrt(J.eps2 + qs / 8.0);
+                    const double gt_here = G[3u * npad + p];
                     double c[8];
 #pragma unroll
                     for (int d = 0; d < 4; ++d) {
-                        c[2 * d] = scale * G[(uint32_t)d * npad + p - sd[d]] * rsqrt(J.eps2 + q[2 * d]);
-                        c[2 * d + 1] = scale * G[(uint32_t)d * npad + p] * rsqrt(J.eps2 + q[2 * d + 1]);
+                        const double gm = d == 3 ? gt_below : G[(uint32_t)d * npad + p - sd[d]];
+                        const double gp = d == 3 ? gt_here : G[(uint32_t)d * npad + p];
+                        c[2 * d] = scale * gm * rsqrt(J.eps2 + q[2 * d]);
+                        c[2 * d + 1] = scale * gp * rsqrt(J.eps2 + q[2 * d + 1]);
                     }
+                    gt_below = gt_here;
                     double D = 1.0, bfull = w0, off = 0.0;
 #pragma unroll
                     for (int f = 0; f < 8; ++f) D += c[f];
@@ -154,8 +206,8 @@ __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
                         if (idx[d] == nn[d]) bfull += c[2 * d + 1] * wp[d];
                     }
                     const double r0 = (w0 + off) - D * w0;
-                    acc_b = bfull * bfull;
-                    acc_r = r0 * r0;
+                    acc_b += bfull * bfull;
+                    acc_r += r0 * r0;
                     const uint32_t irow = ((uint32_t)(l - 1) * J.n3 + (uint32_t)(k - 1)) * J.n2 + (uint32_t)(j - 1);
                     const uint32_t qf = irow * (uint32_t)J.half + m;
                     const uint32_t ci = bctile(J, colour, qf);
@@ -171,6 +223,8 @@ __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
                     const u32x4 rec = {hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16), hb[4] | (hb[5] << 16),
                                        hb[6] | (hb[7] << 16)};
                     c16[(uint32_t)colour * (uint32_t)J.ntq * kTileSlots + qf] = rec;
+#pragma unroll
+                    for (int e = 0; e < 7; ++e) { Am[e] = Ac[e]; Ac[e] = Ap[e]; }
                 }
             }
             const double bb = wave_sum(acc_b);
@@ -190,7 +244,8 @@ __global__ __launch_bounds__(kBlock) void kb_assemble_decide(BTable T)
     __shared__ double lds[4];
     for (int jb = blockIdx.x; jb < T.n_jobs; jb += gridDim.x) {
         const BJob& J = T.jobs[jb];
-        const int np = (int)(kWaves * ((J.nint + kItem - 1) / kItem));
+        const int64_t nfr = (int64_t)J.n1 * J.n2 * J.n3;
+        const int np = (int)(kWaves * ((nfr + kItem - 1) / kItem));
         const double B2 = sum_partials(J.part_a, np, lds);
         const double R2 = sum_partials(J.part_b, np, lds);
         if (threadIdx.x == 0) {
@@ -797,7 +852,7 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
         J.centres = bj.centres;
         hj[q] = J;
         asm_start[q + 1] = asm_start[q] + J.nip;
-        int_start[q + 1] = int_start[q] + (J.nint + kItem - 1) / kItem;
+        int_start[q + 1] = int_start[q] + ((int64_t)J.n1 * J.n2 * J.n3 + kItem - 1) / kItem;   // frame items
         col_start[q + 1] = col_start[q] + J.nit;
         both_start[q + 1] = both_start[q] + 2 * J.nit;
         ball_start[q + 1] = ball_start[q] + J.nc;

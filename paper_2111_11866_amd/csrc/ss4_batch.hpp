@@ -47,7 +47,7 @@ struct BTable {
     BJob* jobs;
     Ctrl* out;            // gathered per-job control blocks (n_jobs)
     int64_t* asm_start;   // prefix of nip
-    int64_t* int_start;   // prefix of interior items ceil(nint / kItem)
+    int64_t* int_start;   // prefix of frame items ceil(n1 n2 n3 / kItem) (the assembly marches the frames)
     int64_t* col_start;   // prefix of nit
     int64_t* both_start;  // prefix of 2*nit
     int64_t* ball_start;  // prefix of nc

@@ -52,6 +52,7 @@ int hip_fail(hipError_t e, const char* what);
 // (occupancy x compute units, a multiple of kXcd, at most kGridCap), so a
 // grid-stride kernel never runs a partial second round of blocks.
 int resident_grid(const void* kernel);
+int resident_grid_bs(const void* kernel, int block);   // the same for blocks of `block` threads
 
 // preparation (prepare.hip)
 int run_prepare(const WsPlan& P, double h, const void* image, int dtype,

@@ -484,6 +484,12 @@ int sweep_grid(const Layout& L, int variant)
         const int64_t g = work < res ? work : res;
         return (int)((g + kXcd - 1) / kXcd * kXcd);
     }
+    if (variant == 3) {
+        work = (int64_t)L.ntm * ((L.n2 + 7) >> 3) * L.n3;
+        res = resident_grid_bs(reinterpret_cast<const void*>(&k_sweep_t2<0, 8>), 512) / 2;
+        const int64_t g = work < res ? work : res;
+        return (int)((g + kXcd - 1) / kXcd * kXcd);
+    }
     if (variant == 1) {
         // half the resident size: fewer streams in flight per XCD keep DRAM
         // pages and the shared neighbour rows better (measured on the
@@ -510,6 +516,9 @@ int sweep_variant(const Layout& L)
     static const char* env = getenv("SUBSURF4D_SWEEP");
     if (env && env[0] == 'r') return 0;
     if (env && env[0] == 't') return 1;
+    // 3: the two-cell form with 8 y-rows per block (fewer neighbour rows
+    // outside each column tile); SUBSURF4D_SWEEP=8 selects it
+    if (env && env[0] == '8') return wide ? 3 : 1;
     return wide ? 2 : 1;
 }
 
@@ -568,13 +577,15 @@ int run_sor_loop(const WsPlan& P, const subsurf4d_step_params& sp, void* ws, hip
         red.uin = ured[(k - 1) & 1];
         red.uout = ured[k & 1];
         red.check = (k >= 2) && (((k - 1) % check_every == 0) || (k - 1 >= max_iter));
-        if (variant == 2) k_sweep_t2<0><<<grid, kBlock, 0, s>>>(red);
+        if (variant == 3) k_sweep_t2<0, 8><<<grid, 512, 0, s>>>(red);
+        else if (variant == 2) k_sweep_t2<0><<<grid, kBlock, 0, s>>>(red);
         else if (variant == 1) k_sweep_tm<0><<<grid, kBlock, 0, s>>>(red);
         else k_sweep<0><<<grid, kBlock, 0, s>>>(red);
         if (k <= max_iter) {
             black.k = k;
             black.uoth = ured[k & 1];
-            if (variant == 2) k_sweep_t2<1><<<grid, kBlock, 0, s>>>(black);
+            if (variant == 3) k_sweep_t2<1, 8><<<grid, 512, 0, s>>>(black);
+            else if (variant == 2) k_sweep_t2<1><<<grid, kBlock, 0, s>>>(black);
             else if (variant == 1) k_sweep_tm<1><<<grid, kBlock, 0, s>>>(black);
             else k_sweep<1><<<grid, kBlock, 0, s>>>(black);
         }

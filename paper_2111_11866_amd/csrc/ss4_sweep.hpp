@@ -68,19 +68,45 @@ __device__ __forceinline__ void st2_stream(double* p, dvec2 v)
 #endif
 }
 
+// Sum over a block of NW waves in a fixed order (the 4-wave case is
+// block_sum); valid in thread 0.
+template <int NW>
+__device__ __forceinline__ double block_sum_w(double v, double* lds)
+{
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        t = lds[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) t += lds[w];
+    }
+    __syncthreads();
+    return t;
+}
+
+template <int NW>
+__device__ __forceinline__ double sum_partials_w(const double* part, int n, double* lds)
+{
+    double s = 0.0;
+    for (int q = threadIdx.x; q < n; q += 64 * NW) s += part[q];
+    return block_sum_w<NW>(s, lds);
+}
+
 // End of a half-sweep: per-block partial of the squared residual rows; for a
 // checking red sweep the last block adds the black partials of the same
 // iterate and applies the stopping rule to iterate k-1.
-template <int COLOR>
+template <int COLOR, int NW = 4>
 __device__ __forceinline__ void finish_sweep(const SweepArgs& a, double acc, double* lds, int* flag)
 {
     Ctrl* C = a.C;
-    const double bs = block_sum(acc, lds);
+    const double bs = block_sum_w<NW>(acc, lds);
     if (threadIdx.x == 0) a.part[blockIdx.x] = bs;
     if (COLOR == 1 || !a.check) return;
     if (!arrive_last(&C->arrive[1], gridDim.x, flag)) return;
-    const double Rr = sum_partials(a.part, gridDim.x, lds);
-    const double Rb = sum_partials(a.part_other, gridDim.x, lds);
+    const double Rr = sum_partials_w<NW>(a.part, gridDim.x, lds);
+    const double Rb = sum_partials_w<NW>(a.part_other, gridDim.x, lds);
     if (threadIdx.x == 0) {
         const int kk = a.k - 1;
         const double R2 = Rb + Rr;
@@ -237,18 +263,19 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tm(SweepArgs a)
 // Half-sweep, frame-marching with two cells per lane (rows of >= 64 slots,
 // whose u rows are 128-byte aligned): a wave covers one 128-slot coefficient
 // tile of one row, lane t owns slots m = 2t, 2t+1, and every stream moves 16
-// bytes per lane.  A block walks column tiles (128 slots x 4 y-rows at one z),
-// marching over the frames of each; tiles are dealt as for k_sweep_tm.
-template <int COLOR>
-__global__ __launch_bounds__(kBlock) void k_sweep_t2(SweepArgs a)
+// bytes per lane.  A block of NW waves walks column tiles (128 slots x NW
+// y-rows at one z), marching over the frames of each; tiles are dealt as for
+// k_sweep_tm.
+template <int COLOR, int NW = 4>
+__global__ __launch_bounds__(64 * NW) void k_sweep_t2(SweepArgs a)
 {
-    __shared__ double lds[4];
+    __shared__ double lds[NW];
     __shared__ int flag;
     Ctrl* C = a.C;
     if (C->done) return;
     const Layout& L = a.L;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int njb = (L.n2 + 3) >> 2;
+    const int njb = (L.n2 + NW - 1) / NW;
     const int64_t ncol = (int64_t)L.ntm * njb * L.n3;
     const int64_t sy = L.rs, sz = (int64_t)L.p2 * L.rs, st = (int64_t)L.p2 * L.p3 * L.rs;
     const int64_t cst = (int64_t)L.n2 * L.n3 * L.ntm * kTileVals;
@@ -261,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_t2(SweepArgs a)
         const int64_t t2 = tw.t / L.ntm;
         const int k = (int)(t2 % L.n3) + 1;
         const int jb = (int)(t2 / L.n3);
-        const int j = jb * 4 + ty + 1;
+        const int j = jb * NW + ty + 1;
         const int m = mt * kTileSlots + 2 * tx;
         const bool jok = j <= L.n2;                      // uniform across the wave
         const bool sok = jok && m <= last_slot;
@@ -324,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_t2(SweepArgs a)
             Bc = Bp;
         }
     }
-    finish_sweep<COLOR>(a, acc, lds, &flag);
+    finish_sweep<COLOR, NW>(a, acc, lds, &flag);
 }
 
 }  // namespace

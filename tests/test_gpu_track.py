@@ -93,3 +93,28 @@ def test_track_capacity_and_empty():
     with pytest.raises(B.Subsurf4dError) as e:
         B.track(n, torch.from_numpy(u).to("cuda"), 0.5, capacity=3)
     assert e.value.status == B.EWORKSPACE
+
+
+def test_track_nuclei_crop_against_oracle_and_edt():
+    """A config-2-like crop (160 x 160 x 48 voxels, 4 frames, 120 Brownian
+    nuclei) thresholded as the segmentation: labels equal the oracle's flood
+    fill; distances equal scipy's exact Euclidean transform (pinned against
+    the oracle's brute force in the CPU tests; the brute force is too slow
+    here); the cell records equal the oracle's records built from those."""
+    ndi = pytest.importorskip("scipy.ndimage")
+    n = (160, 160, 48, 4)
+    img = synth.nuclei_cfg2(n=n, n_nuclei=120, geom_seed=31, noise_seed=32)
+    u = np.zeros(orc.padded_shape(n))
+    u[1:-1, 1:-1, 1:-1, 1:-1] = img.image.astype(np.float64) / 255.0
+    level = 0.35
+    cells, lab, d2 = gpu_track(n, u, level)
+    ref_lab = orc.track_label(n, u, level)
+    assert np.array_equal(lab, ref_lab)
+    ref_d2 = np.empty_like(d2)
+    for l in range(n[3]):
+        edt = ndi.distance_transform_edt(np.pad(ref_lab[l] >= 0, 1))[1:-1, 1:-1, 1:-1]
+        ref_d2[l] = np.rint(edt ** 2).astype(np.int32)
+    assert np.array_equal(d2, ref_d2)
+    ref_cells = orc.track_cells(n, ref_lab, ref_d2)
+    same_cells(cells, ref_cells)
+    assert len(cells) > 100 and (cells["kind"][cells["frame"] > 0] > 0).mean() > 0.5
