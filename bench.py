@@ -572,18 +572,21 @@ def main():
                          "frac_of_peak": 2 * nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     del src, dst
     # read-dominated probes: k streams of 1 GiB summed into one (k = 2: the
-    # STREAM triad's mix; k = 11: about the FP64 sweep's 11 reads per write)
+    # STREAM triad's mix; k = 11: about the FP64 sweep's 11 reads per write),
+    # and the same 11 streams read with no write stream
     chunk = 1 << 30
     out["stream_probe"] = {}
-    for k in (2, 11):
+    for k, w in ((2, 1), (11, 1), (11, 0)):
         src = torch.ones(k * chunk // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty(chunk // 8, dtype=torch.float64, device="cuda")
-        ms = B.stream_probe(src, dst, k, reps=5)
-        moved = (k + 1) * chunk
-        out["stream_probe"][f"reads_{k}_per_write"] = {"bytes_moved": moved, "ms": ms,
-                                                        "GBs": moved / (ms * 1e-3) / 1e9,
-                                                        "frac_of_peak": moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        ms = B.stream_probe(src, dst, k, writes=w, reps=5)
+        moved = (k + w) * chunk
+        key = f"reads_{k}_per_write" if w else f"reads_{k}_no_write"
+        out["stream_probe"][key] = {"bytes_moved": moved, "ms": ms, "GBs": moved / (ms * 1e-3) / 1e9,
+                                    "frac_of_peak": moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         del src, dst
+    out["stream_probe"]["sweep_vs_11_per_write"] = (
+        achieved / out["stream_probe"]["reads_11_per_write"]["GBs"])
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()

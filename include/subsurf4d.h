@@ -296,16 +296,21 @@ int subsurf4d_solve(const subsurf4d_grid* grid, const double* coef, const double
 int subsurf4d_copy_probe(const void* src, void* dst, size_t bytes, int32_t reps, double* ms, void* stream);
 
 /*
- * Read-dominated bandwidth probe (the sweeps read about 11 streams per one
- * written): dst[i] = sum over r < reads of src[r*n + i], n = bytes/16 16-byte
- * elements, once untimed and then `reps` times between two HIP events on
- * `stream`; *ms (host) receives the mean time of one pass, which moves
- * (reads + 1) * bytes.  src (device) holds reads * bytes, dst (device) bytes,
- * both 16-byte aligned, not overlapping; reads in [1, 16].  Synchronises
- * `stream`.  Not part of the method.
+ * Read-dominated bandwidth probe (the FP64 sweeps read about 11 streams per
+ * one written).  src (device) holds `reads` chunks of n = bytes/16 16-byte
+ * elements (reads * bytes), reads in [1, 16].  writes = 1: dst (device, bytes)
+ * receives dst[i] = sum over r < reads of src[r*n + i], a pass moving
+ * (reads + 1) * bytes.  writes = 0: reads only; dst receives one 16-byte
+ * partial sum per block of the launch in its first
+ * min(65536, ceil(n / 1024)) elements (their total is the sum of all of src),
+ * so it must hold that many.  Each pass runs once untimed and then `reps`
+ * times between two HIP events on `stream`; *ms (host) receives the mean time
+ * of one pass.  Buffers 16-byte aligned, not overlapping.  Synchronises
+ * `stream`.  Not part of the method: it states the HBM rate this chip gives
+ * the sweeps' mix of reads and writes.
  */
-int subsurf4d_stream_probe(const void* src, void* dst, size_t bytes, int32_t reads, int32_t reps, double* ms,
-                           void* stream);
+int subsurf4d_stream_probe(const void* src, void* dst, size_t bytes, int32_t reads, int32_t writes, int32_t reps,
+                           double* ms, void* stream);
 
 /*
  * Batched time step over many independent windows (the per-nucleus windows

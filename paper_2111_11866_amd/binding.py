@@ -177,7 +177,7 @@ def lib():
         L.subsurf4d_timing.argtypes = [I, P, P, P, P]
         L.subsurf4d_timing.restype = None
         L.subsurf4d_copy_probe.argtypes = [P, P, SZ, I, P, P]
-        L.subsurf4d_stream_probe.argtypes = [P, P, SZ, I, I, P, P]
+        L.subsurf4d_stream_probe.argtypes = [P, P, SZ, I, I, I, P, P]
         L.subsurf4d_batch_workspace_bytes.argtypes = [ctypes.POINTER(Grid), I]
         L.subsurf4d_batch_workspace_bytes.restype = SZ
         L.subsurf4d_prepare_workspace_bytes.argtypes = [ctypes.POINTER(Grid), I]
@@ -405,13 +405,22 @@ def solve_async(n, h, coef, b, u, params: StepParams, ws, result=None, stream=No
                                  _p(ws, "workspace"), _nb(ws), _stream(stream)))
 
 
-def stream_probe(src, dst, reads, reps=10, stream=None) -> float:
-    """Mean ms of one pass dst = sum of `reads` chunks of src (each the size of dst)."""
+def stream_probe(src, dst, reads, writes=1, reps=10, stream=None) -> float:
+    """Mean ms of one pass over `reads` chunks of src, each the size of dst:
+    writes=1: dst = their element-wise sum; writes=0: reads only, dst[:g]
+    receives per-block partial sums (g = stream_probe_blocks(dst))."""
     ms = ctypes.c_double(0.0)
     nbytes = _nb(dst)
     _check(lib().subsurf4d_stream_probe(_p(src, "src", None, reads * nbytes), _p(dst, "dst"), nbytes, int(reads),
-                                        int(reps), ctypes.byref(ms), _stream(stream)))
+                                        int(writes), int(reps), ctypes.byref(ms), _stream(stream)))
     return ms.value
+
+
+def stream_probe_blocks(dst) -> int:
+    """Blocks of a stream-probe launch over chunks of dst's size (partial sums
+    written by a read-only pass)."""
+    n = _nb(dst) // 16
+    return min(65536, -(-n // 1024))
 
 
 def timing(op: int = 3) -> dict:

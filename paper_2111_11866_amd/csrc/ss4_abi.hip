@@ -440,16 +440,17 @@ int subsurf4d_solve(const subsurf4d_grid* grid, const double* coef, const double
     SS4_GUARD_END
 }
 
-int subsurf4d_stream_probe(const void* src, void* dst, size_t bytes, int32_t reads, int32_t reps, double* ms,
-                           void* stream)
+int subsurf4d_stream_probe(const void* src, void* dst, size_t bytes, int32_t reads, int32_t writes, int32_t reps,
+                           double* ms, void* stream)
 {
     SS4_GUARD_BEGIN
     g_error.clear();
-    if (!src || !dst || !ms || reps < 1 || reads < 1 || reads > 16) return fail(SUBSURF4D_EINVAL, "bad arguments");
+    if (!src || !dst || !ms || reps < 1 || reads < 1 || reads > 16 || writes < 0 || writes > 1)
+        return fail(SUBSURF4D_EINVAL, "bad arguments");
     if (bytes == 0 || bytes % 16 != 0) return fail(SUBSURF4D_EINVAL, "bytes must be a positive multiple of 16");
     if (reinterpret_cast<uintptr_t>(src) % 16 != 0 || reinterpret_cast<uintptr_t>(dst) % 16 != 0)
         return fail(SUBSURF4D_EINVAL, "buffers must be 16-byte aligned");
-    return run_stream_probe(src, dst, bytes, reads, reps, ms, static_cast<hipStream_t>(stream));
+    return run_stream_probe(src, dst, bytes, reads, writes, reps, ms, static_cast<hipStream_t>(stream));
     SS4_GUARD_END
 }
 

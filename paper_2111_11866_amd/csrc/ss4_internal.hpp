@@ -81,7 +81,9 @@ int run_unsplit(const WsPlan& P, double* u, void* ws, hipStream_t s);
 int launch_assembly(const WsPlan& P, double h, const double* G, const double* w, const double* ub,
                     const subsurf4d_step_params& sp, void* coef16, void* ws, hipStream_t s);
 int run_copy_probe(const void* src, void* dst, size_t bytes, int reps, double* ms, hipStream_t s);
-int run_stream_probe(const void* src, void* dst, size_t bytes, int reads, int reps, double* ms, hipStream_t s);
+int stream_probe_grid(size_t bytes);
+int run_stream_probe(const void* src, void* dst, size_t bytes, int reads, int writes, int reps, double* ms,
+                     hipStream_t s);
 
 // batched windows (batch.hip)
 size_t batch_job_bytes(const int32_t n[4], int32_t nc);

@@ -64,7 +64,19 @@ __device__ __forceinline__ void assembly_decide(const AsmArgs& a, double acc_b, 
 // its 8 faces; the colour-split tiles (MODE kSplit) or the natural arrays
 // (kNatural) receive them.  Shared by both assembly kernels, so the
 // coefficients do not depend on the visiting order.
-template <int MODE, typename WAt, typename GAt>
+// Store of an assembly output: non-temporal (NTS) for the column kernel, so
+// that the ~90 B per cell written do not push the neighbour planes of w and G
+// that the adjacent blocks are about to read out of L2.
+template <bool NTS, typename T>
+__device__ __forceinline__ void put(T* p, T v)
+{
+    if (NTS) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int MODE, bool NTS, typename WAt, typename GAt>
 __device__ __forceinline__ void assemble_cell(const AsmArgs& a, int64_t p, int i, int j, int k, int l, int colour,
                                               int m, WAt&& wat, GAt&& gat, double& acc_b, double& acc_r)
 {
@@ -140,15 +152,15 @@ __device__ __forceinline__ void assemble_cell(const AsmArgs& a, int64_t p, int i
     if (MODE == kSplit) {
         const int64_t ci = ctile(L, colour, irow, m);
 #pragma unroll
-        for (int f = 0; f < 8; ++f) a.coef[ci + f * kTileSlots] = c[f];
-        a.coef[ci + 8 * kTileSlots] = w0;
+        for (int f = 0; f < 8; ++f) put<NTS>(a.coef + ci + f * kTileSlots, c[f]);
+        put<NTS>(a.coef + ci + 8 * kTileSlots, w0);
         if (a.coef16) {
             const double inv = 1.0 / D;
             uint32_t h[8];
 #pragma unroll
             for (int f = 0; f < 8; ++f) h[f] = bf16_bits((float)(c[f] * inv));
-            a.coef16[mrec(L, colour, irow, m)] =
-                make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+            const u32x4 rec = {h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16)};
+            put<NTS>(reinterpret_cast<u32x4*>(a.coef16 + mrec(L, colour, irow, m)), rec);
         }
     } else {
         const int64_t qi = irow * L.n1 + (i - 1);
@@ -188,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
         if (!inside) continue;
         const int64_t s2 = L.p1, s3 = (int64_t)L.p1 * L.p2, s4 = s3 * L.p3;
         const int64_t sd[4] = {1, s2, s3, s4};
-        assemble_cell<MODE>(
+        assemble_cell<MODE, false>(
             a, p, i, j, k, l, colour, m,
             [&](int di, int dj, int dk, int dl) { return a.w[p + di + dj * s2 + dk * s3 + dl * s4]; },
             [&](int d, int plus) { return a.G[(int64_t)d * L.npad + p - (plus ? 0 : sd[d])]; }, acc_b, acc_r);
@@ -210,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
 constexpr int kAx = 66, kAy = 6, kAz = 3;                  // slab: x with halo, y rows with halo, z planes
 constexpr int kSlab = kAx * kAy * kAz;                     // doubles per frame slot
 
-template <bool PREFETCH>
+template <bool PREFETCH, bool NTS>
 __global__ __launch_bounds__(kBlock) void k_assemble_cols(AsmArgs a)
 {
     __shared__ double lds[4];
@@ -287,11 +299,11 @@ __global__ __launch_bounds__(kBlock) void k_assemble_cols(AsmArgs a)
                 const int m = (i - 1) >> 1;
                 const double w0 = slab[l % 3][(1 * kAy + ty + 1) * kAx + tx + 1];
                 const int64_t us = prow * L.rs + L.xoff + m;
-                if (colour == 0) { a.ured0[us] = w0; a.ured1[us] = w0; }
-                else a.ublack[us] = w0;
+                if (colour == 0) { put<NTS>(a.ured0 + us, w0); put<NTS>(a.ured1 + us, w0); }
+                else put<NTS>(a.ublack + us, w0);
                 const double gt_here = a.G[3 * L.npad + p];
                 const int sl[3] = {(l + 2) % 3, l % 3, (l + 1) % 3};      // slots of frames l-1, l, l+1
-                assemble_cell<kSplit>(
+                assemble_cell<kSplit, NTS>(
                     a, p, i, j, k, l, colour, m,
                     [&](int di, int dj, int dk, int dl) {
                         return slab[sl[dl + 1]][((dk + 1) * kAy + ty + 1 + dj) * kAx + tx + 1 + di];
@@ -411,19 +423,49 @@ __global__ __launch_bounds__(kBlock) void k_copy_probe(const double2* __restrict
         dst[q] = src[q];
 }
 
-// Read-dominated probe: dst = sum of `reads` source chunks of n 16-byte
-// elements each (reads streams in, one out, as the sweeps' traffic mix).
+// Read-dominated probe over `reads` source chunks of n 16-byte elements.
+// WRITE: dst = element-wise sum of the chunks (reads streams in, one out, as
+// the sweeps' traffic mix); otherwise dst[block] = the block's share of the
+// total (reads only).  Each thread keeps kProbeU non-temporal 16-byte loads
+// per chunk in flight, which is what it takes to reach the chip's streaming
+// rate.
+constexpr int kProbeU = 4;
+
+template <bool WRITE>
 __global__ __launch_bounds__(kBlock) void k_stream_probe(const double2* __restrict__ src, double2* __restrict__ dst,
                                                          int64_t n, int reads)
 {
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
-        double2 acc = src[q];
-        for (int r = 1; r < reads; ++r) {
-            const double2 v = src[(int64_t)r * n + q];
-            acc.x += v.x;
-            acc.y += v.y;
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    const dv2* s = reinterpret_cast<const dv2*>(src);
+    dv2* d = reinterpret_cast<dv2*>(dst);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    dv2 tot = {0.0, 0.0};
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; base < n; base += stride * kProbeU) {
+        dv2 acc[kProbeU];
+#pragma unroll
+        for (int u = 0; u < kProbeU; ++u) acc[u] = dv2{0.0, 0.0};
+#pragma unroll 2
+        for (int r = 0; r < reads; ++r) {
+            const dv2* sr = s + (int64_t)r * n;
+#pragma unroll
+            for (int u = 0; u < kProbeU; ++u) {
+                const int64_t q = base + u * stride;
+                if (q < n) acc[u] += __builtin_nontemporal_load(sr + q);
+            }
         }
-        dst[q] = acc;
+#pragma unroll
+        for (int u = 0; u < kProbeU; ++u) {
+            const int64_t q = base + u * stride;
+            if (q >= n) continue;
+            if (WRITE) __builtin_nontemporal_store(acc[u], d + q);
+            else tot += acc[u];
+        }
+    }
+    if (!WRITE) {
+        __shared__ double lds[4];
+        const double bx = block_sum(tot.x, lds);
+        const double by = block_sum(tot.y, lds);
+        if (threadIdx.x == 0) dst[blockIdx.x] = make_double2(bx, by);
     }
 }
 
@@ -474,13 +516,24 @@ __global__ void k_write_result(const Ctrl* C, subsurf4d_result* res, int sweeps_
     }
 }
 
+// SUBSURF4D_SWEEP_GRID=<percent> sizes the two-cell sweeps' grids as that
+// share of the resident grid (default 50); the tile walk gives the same
+// iterate for any grid.
+int sweep_grid_percent()
+{
+    const char* env = getenv("SUBSURF4D_SWEEP_GRID");
+    const int pc = env ? atoi(env) : 50;
+    return pc < 1 ? 1 : (pc > 400 ? 400 : pc);
+}
+
 int sweep_grid(const Layout& L, int variant)
 {
     int64_t work;
     int res;
     if (variant == 2) {
         work = (int64_t)L.ntm * ((L.n2 + 3) >> 2) * L.n3;
-        res = resident_grid(reinterpret_cast<const void*>(&k_sweep_t2<0>)) / 2;
+        res = (int)((int64_t)resident_grid(reinterpret_cast<const void*>(&k_sweep_t2<0>)) * sweep_grid_percent() / 100);
+        if (res > kGridCap) res = kGridCap;    // the per-block partial arrays hold kGridCap entries
         const int64_t g = work < res ? work : res;
         return (int)((g + kXcd - 1) / kXcd * kXcd);
     }
@@ -513,7 +566,7 @@ int sweep_grid(const Layout& L, int variant)
 int sweep_variant(const Layout& L)
 {
     const bool wide = L.half >= 64;   // 128-byte aligned u rows, pairs stay in the row
-    static const char* env = getenv("SUBSURF4D_SWEEP");
+    const char* env = getenv("SUBSURF4D_SWEEP");     // read per solve, so a process can switch
     if (env && env[0] == 'r') return 0;
     if (env && env[0] == 't') return 1;
     // 3: the two-cell form with 8 y-rows per block (fewer neighbour rows
@@ -650,18 +703,30 @@ int run_copy_probe(const void* src, void* dst, size_t bytes, int reps, double* m
     return 0;
 }
 
-int run_stream_probe(const void* src, void* dst, size_t bytes, int reads, int reps, double* ms, hipStream_t s)
+int stream_probe_grid(size_t bytes)
+{
+    const int64_t n = (int64_t)(bytes / 16);
+    const int64_t g = (n + (int64_t)kBlock * kProbeU - 1) / ((int64_t)kBlock * kProbeU);
+    return (int)(g < 65536 ? g : 65536);
+}
+
+int run_stream_probe(const void* src, void* dst, size_t bytes, int reads, int writes, int reps, double* ms,
+                     hipStream_t s)
 {
     const int64_t n = (int64_t)(bytes / 16);
     hipEvent_t a, b;
     SS4_HIP(hipEventCreate(&a));
     SS4_HIP(hipEventCreate(&b));
-    const int grid = 8192;
+    const int grid = stream_probe_grid(bytes);
     const double2* sp = static_cast<const double2*>(src);
     double2* dp = static_cast<double2*>(dst);
-    k_stream_probe<<<grid, kBlock, 0, s>>>(sp, dp, n, reads);
+    auto launch = [&] {
+        if (writes) k_stream_probe<true><<<grid, kBlock, 0, s>>>(sp, dp, n, reads);
+        else k_stream_probe<false><<<grid, kBlock, 0, s>>>(sp, dp, n, reads);
+    };
+    launch();
     SS4_HIP(hipEventRecord(a, s));
-    for (int r = 0; r < reps; ++r) k_stream_probe<<<grid, kBlock, 0, s>>>(sp, dp, n, reads);
+    for (int r = 0; r < reps; ++r) launch();
     SS4_HIP(hipEventRecord(b, s));
     SS4_HIP(hipEventSynchronize(b));
     float t = 0.f;
@@ -726,15 +791,22 @@ int launch_assembly(const WsPlan& P, double h, const double* G, const double* w,
     // frame issued after the barrier and kept in flight during the cell
     // arithmetic (1), or issued just before the frame's LDS store (0); both
     // give the same bits
-    static const char* env = getenv("SUBSURF4D_ASM_PREFETCH");
+    // SUBSURF4D_ASM_NT=0|1: plain or non-temporal stores of the outputs (same bits)
+    const char* env = getenv("SUBSURF4D_ASM_PREFETCH");
+    const char* env_nt = getenv("SUBSURF4D_ASM_NT");
     const bool prefetch = !(env && env[0] == '0');
-    const void* kern = prefetch ? reinterpret_cast<const void*>(&k_assemble_cols<true>)
-                                : reinterpret_cast<const void*>(&k_assemble_cols<false>);
+    const bool nts = !(env_nt && env_nt[0] == '0');
+    const void* kern = prefetch ? (nts ? reinterpret_cast<const void*>(&k_assemble_cols<true, true>)
+                                       : reinterpret_cast<const void*>(&k_assemble_cols<true, false>))
+                                : (nts ? reinterpret_cast<const void*>(&k_assemble_cols<false, true>)
+                                       : reinterpret_cast<const void*>(&k_assemble_cols<false, false>));
     const int res = resident_grid(kern);
     const int64_t g = ncol < res ? ncol : res;
     const int grid = (int)((g + kXcd - 1) / kXcd * kXcd);
-    if (prefetch) k_assemble_cols<true><<<grid, kBlock, 0, s>>>(a);
-    else k_assemble_cols<false><<<grid, kBlock, 0, s>>>(a);
+    if (prefetch && nts) k_assemble_cols<true, true><<<grid, kBlock, 0, s>>>(a);
+    else if (prefetch) k_assemble_cols<true, false><<<grid, kBlock, 0, s>>>(a);
+    else if (nts) k_assemble_cols<false, true><<<grid, kBlock, 0, s>>>(a);
+    else k_assemble_cols<false, false><<<grid, kBlock, 0, s>>>(a);
     SS4_LAUNCHED("assemble");
     return 0;
 }

@@ -505,7 +505,9 @@ def test_deterministic_repeat(cfg1):
 
 
 def test_stream_probe_sums_chunks():
-    """The read-dominated bandwidth probe computes dst = sum of its source chunks."""
+    """The read-dominated bandwidth probe computes dst = sum of its source
+    chunks (writes=1), or per-block partial sums whose total is the sum of the
+    whole source (writes=0); integer-valued data, so both are exact."""
     n = 1 << 16
     src = torch.arange(3 * 2 * n, dtype=torch.float64, device=DEV)
     dst = torch.empty(2 * n, dtype=torch.float64, device=DEV)
@@ -513,6 +515,13 @@ def test_stream_probe_sums_chunks():
     assert ms > 0.0
     want = src.view(3, 2 * n).sum(0)
     assert torch.equal(dst, want)
+    g = B.stream_probe_blocks(dst)
+    assert g == n // 1024
+    dst.fill_(-1.0)
+    ms = B.stream_probe(src, dst, 3, writes=0, reps=2)
+    assert ms > 0.0
+    assert float(dst[: 2 * g].sum()) == float(src.sum())
+    assert bool((dst[2 * g:] == -1.0).all())
 
 
 def test_red_phase_reads_only_black():
