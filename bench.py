@@ -499,7 +499,7 @@ def main():
             # in the mixed form omega relaxes only the inner FP32 sweeps; the FP64
             # residual and refine_tol decide the result
             msp = replace(sp, precision=B.MIXED, refine_tol=rtol, inner_sweeps=args.inner,
-                          omega=args.inner_omega)
+                          omega=args.inner_omega, flags=B.FLAG_SHORT_LAST_PASS)
             job.init(v=1.0, R=8.0, ball_r=sp.ball_r)
             for w in range(args.warmup):
                 job.step(msp)
@@ -515,13 +515,17 @@ def main():
             mlaunch = mt["sweep_ms"] / max(mt["sweep_launches"], 1)
             # 32 B per update, except the first iteration of each pass, which
             # starts from d = 0: red 8 B (r/D read, d written), black 28 B
-            m_in = args.inner
-            mbytes = cells / 2.0 * (64.0 * m_in - 28.0) / (2.0 * m_in)
+            # (passes run inner_sweeps iterations, or fewer when the last one is shortened)
+            n_it = max(sum(r["iterations"] for r in recs), 1)
+            n_pass = sum(r["outer"] for r in recs)
+            mbytes = cells / 2.0 * (64.0 * n_it - 28.0 * n_pass) / (2.0 * n_it)
             out.setdefault("mixed", {})[tol_name] = {
                 "ms_per_step": mdt * 1e3 / mixed_steps,
                 "speedup_vs_fp64_step": (dt / args.steps) / (mdt / mixed_steps),
                 "refinement_passes": [r["outer"] for r in recs],
                 "inner_sweeps_per_pass": args.inner,
+                "inner_sweeps_per_step": [r["iterations"] for r in recs],
+                "short_last_pass": True,
                 "inner_omega": args.inner_omega,
                 "final_rel_residual": [r["rel_res"] for r in recs],
                 "inner_sweep_avg_launch_ms": mlaunch,

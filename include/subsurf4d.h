@@ -136,6 +136,15 @@ typedef struct {
  * does not report.  Only kernel launches are enqueued (no memset or copy), so
  * the call can be captured in a HIP graph and replayed. */
 #define SUBSURF4D_FLAG_ASYNC 8
+/* subsurf4d_step_params.flags, MIXED, synchronous step and solve calls: from
+ * the third refinement pass on, the host shortens a pass to the FP32
+ * iterations that the contraction measured over the previous pass predicts
+ * for reaching refine_tol (x 1.25, + 1), never beyond inner_sweeps.  The
+ * stopping rule is still the FP64 residual's, so the result meets refine_tol
+ * as without the flag; only the number of inner iterations differs
+ * (result->iterations counts them).  Ignored with SUBSURF4D_FLAG_ASYNC, by
+ * FP64 steps and by the batched step. */
+#define SUBSURF4D_FLAG_SHORT_LAST_PASS 16
 
 /* Outcome of a solve.  Iterations are full red-black iterations. */
 typedef struct {

@@ -60,6 +60,7 @@ FLAG_NO_GRAPH = 1
 FLAG_SWEEP_FLAT = 2
 FLAG_SWEEP_MARCH = 4
 FLAG_ASYNC = 8
+FLAG_SHORT_LAST_PASS = 16
 
 
 class BatchJobC(ctypes.Structure):

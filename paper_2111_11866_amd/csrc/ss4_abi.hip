@@ -175,7 +175,7 @@ int check_step_params(const subsurf4d_step_params* p)
             return fail(SUBSURF4D_EINVAL, "inner_sweeps must be in [1, 1024]");
     }
     const int known = SUBSURF4D_FLAG_NO_GRAPH | SUBSURF4D_FLAG_SWEEP_FLAT | SUBSURF4D_FLAG_SWEEP_MARCH |
-                      SUBSURF4D_FLAG_ASYNC;
+                      SUBSURF4D_FLAG_ASYNC | SUBSURF4D_FLAG_SHORT_LAST_PASS;
     if (p->flags & ~known) return fail(SUBSURF4D_EINVAL, "unknown flags");
     if ((p->flags & SUBSURF4D_FLAG_SWEEP_FLAT) && (p->flags & SUBSURF4D_FLAG_SWEEP_MARCH))
         return fail(SUBSURF4D_EINVAL, "at most one sweep shape flag");

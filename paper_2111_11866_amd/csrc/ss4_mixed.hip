@@ -81,17 +81,20 @@ __global__ __launch_bounds__(kBlock) void k_mx_residual(MxArgs a)
                 if (m < cnt) {
                     const int64_t r = rb + (int64_t)(l - 1) * L.n3 * L.n2;
                     const double* cf = a.coef + ctile(L, colour, r, m);
-                    const double c0 = cf[0], c1 = cf[kTileSlots], c2 = cf[2 * kTileSlots], c3 = cf[3 * kTileSlots];
-                    const double c4 = cf[4 * kTileSlots], c5 = cf[5 * kTileSlots], c6 = cf[6 * kTileSlots];
-                    const double c7 = cf[7 * kTileSlots];
+                    // touched once per residual: non-temporal, so the neighbour rows stay in L2
+                    auto ld = [](const double* p) { return __builtin_nontemporal_load(p); };
+                    const double c0 = ld(cf), c1 = ld(cf + kTileSlots), c2 = ld(cf + 2 * kTileSlots);
+                    const double c3 = ld(cf + 3 * kTileSlots), c4 = ld(cf + 4 * kTileSlots);
+                    const double c5 = ld(cf + 5 * kTileSlots), c6 = ld(cf + 6 * kTileSlots);
+                    const double c7 = ld(cf + 7 * kTileSlots);
                     const double xo = oth[par ? ui - 1 : ui + 1];
-                    double s = cf[8 * kTileSlots];
+                    double s = ld(cf + 8 * kTileSlots);
                     s += c0 * (par ? xo : Bc) + c1 * (par ? Bc : xo);
                     s += c2 * oth[ui - sy] + c3 * oth[ui + sy];
                     s += c4 * oth[ui - sz] + c5 * oth[ui + sz];
                     s += c6 * Bm + c7 * Bp;
                     const double D = ((((((((1.0 + c0) + c1) + c2) + c3) + c4) + c5) + c6) + c7);
-                    const double res = s - D * own[ui];
+                    const double res = s - D * ld(own + ui);
                     acc += res * res;
                     a.rf[mrec(L, colour, r, m)] = (float)(res / D);
                 }
@@ -269,6 +272,7 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
     const int64_t row_tiles = (int64_t)((L.half + 63) >> 6) * ((2 * L.nrow_int + 3) >> 2);
     const int grid_rows = grid_for(row_tiles, 1);
     const int grid_res = resident_grid(reinterpret_cast<const void*>(&k_mx_residual));
+    auto residual = [&]() { k_mx_residual<<<grid_res, kBlock, 0, s>>>(a); };
     const int64_t ncol = (int64_t)((L.half + 63) >> 6) * ((L.n2 + 3) >> 2) * L.n3;
     // one cell per lane: two cells per lane (as the FP64 sweep) measured slower
     // for the FP32 correction, in two designs (3.36 vs 4.13 TB/s on the
@@ -277,10 +281,10 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
     const int res_g = resident_grid(reinterpret_cast<const void*>(&k_mx_sweep<0, false>)) / 2;
     const int grid_cols = (int)(((ncol < res_g ? ncol : res_g) + kXcd - 1) / kXcd * kXcd);
 
-    auto enqueue_sweeps = [&]() {
+    auto enqueue_sweeps = [&](int mm) {
         k_mx_sweep<0, true><<<grid_cols, kBlock, 0, s>>>(a);
         k_mx_sweep<1, true><<<grid_cols, kBlock, 0, s>>>(a);
-        for (int it = 1; it < m; ++it) {
+        for (int it = 1; it < mm; ++it) {
             k_mx_sweep<0, false><<<grid_cols, kBlock, 0, s>>>(a);
             k_mx_sweep<1, false><<<grid_cols, kBlock, 0, s>>>(a);
         }
@@ -290,9 +294,9 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
         // the residual's decision return at once
         for (int pass = 0; pass <= max_outer; ++pass) {
             a.pass = pass;
-            k_mx_residual<<<grid_res, kBlock, 0, s>>>(a);
+            residual();
             if (pass == max_outer) break;
-            enqueue_sweeps();
+            enqueue_sweeps(m);
             k_mx_update<<<grid_rows, kBlock, 0, s>>>(a);
         }
         SS4_LAUNCHED("mixed: refinement passes");
@@ -303,28 +307,47 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
     SS4_HIP(hipMemcpyAsync(&hc, C, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     SS4_HIP(hipStreamSynchronize(s));
     SweepTimer timer(s);
+    const bool shorten = (sp.flags & SUBSURF4D_FLAG_SHORT_LAST_PASS) != 0;
     int pass = 0;
+    int64_t sweeps = 0;       // FP32 red-black iterations enqueued
+    double prev_res = 0.0;    // relative FP64 residual before the previous pass
+    int prev_m = 0;           // that pass's iterations
     while (!hc.done) {
         a.pass = pass;
-        k_mx_residual<<<grid_res, kBlock, 0, s>>>(a);
+        residual();
         SS4_LAUNCHED("mixed: residual");
         SS4_HIP(hipMemcpyAsync(&hc, C, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
         SS4_HIP(hipStreamSynchronize(s));
         if (hc.done) break;
+        int mm = m;
+        if (shorten && pass >= 2 && prev_res > 0.0 && hc.rel_res > 0.0 && hc.rel_res < prev_res &&
+            sp.refine_tol < hc.rel_res) {
+            // per-iteration contraction over the previous pass, and the
+            // iterations it predicts for reaching refine_tol
+            const double rho = pow(hc.rel_res / prev_res, 1.0 / prev_m);
+            const double need = log(sp.refine_tol / hc.rel_res) / log(rho);
+            if (need < (double)m) {
+                const int pred = (int)ceil(1.25 * need) + 1;
+                if (pred < mm) mm = pred;
+            }
+        }
+        prev_res = hc.rel_res;
+        prev_m = mm;
         timer.begin();
-        enqueue_sweeps();
+        enqueue_sweeps(mm);
         timer.end();
         k_mx_update<<<grid_rows, kBlock, 0, s>>>(a);
         SS4_LAUNCHED("mixed: inner sweeps");
+        sweeps += mm;
         ++pass;
         if (timer.end_event()) {
             SS4_HIP(hipEventSynchronize(timer.end_event()));
             timer.collect();
         }
     }
-    timer.account(2 * (int64_t)m * pass, (int64_t)m * pass * L.nint);
+    timer.account(2 * sweeps, sweeps * L.nint);
     res->status = hc.status;
-    res->iterations = hc.outer * m;
+    res->iterations = (int32_t)sweeps;
     res->outer_iterations = hc.outer;
     res->reserved = 0;
     res->rel_residual = hc.rel_res;

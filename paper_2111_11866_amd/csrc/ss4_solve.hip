@@ -213,21 +213,22 @@ __global__ __launch_bounds__(kBlock) void k_assemble(AsmArgs a)
 // staged in LDS: a block owns a column tile of 64 interior x-cells x 4
 // y-rows at one z and walks the frames l = 1..N4.  Per frame it loads the
 // 3 planes (z-1, z, z+1) x 6 rows (y-1 .. y+4) x 66 x-cells of frame l+1
-// into a ring of three frame slots, so every w value comes from LDS and each
-// frame's slab is read from memory once per block.  The t-face G of the frame
+// into a ring of four frame slots (one barrier per frame), so every w value
+// comes from LDS and each frame's slab is read from memory once per block.  The t-face G of the frame
 // below is kept in a register from the previous frame.  Tiles of one XCD are
 // consecutive (x-tile fastest, then z), so the neighbour planes a block loads
 // are loaded by the blocks beside it at about the same time (L2 hits).  Ghost
 // cells are written by k_ghost_split.
 constexpr int kAx = 66, kAy = 6, kAz = 3;                  // slab: x with halo, y rows with halo, z planes
 constexpr int kSlab = kAx * kAy * kAz;                     // doubles per frame slot
+constexpr int kRing = 4;                                   // frame slots: l-1, l, l+1 and the one being filled
 
 template <bool PREFETCH, bool NTS>
 __global__ __launch_bounds__(kBlock) void k_assemble_cols(AsmArgs a)
 {
     __shared__ double lds[4];
     __shared__ int flag;
-    __shared__ double slab[3][kSlab];
+    __shared__ double slab[kRing][kSlab];
     const Layout& L = a.L;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int nxt = (L.n1 + 63) >> 6;
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble_cols(AsmArgs a)
         // slab of frame lf: padded x0-1 .. x0+64, y j0-1 .. j0+4, z k-1 .. k+1; this
         // thread's share (entries threadIdx.x + r*kBlock) goes to registers
         // first, so the loads of frame l+2 are in flight while frame l is
-        // assembled, and then to the ring slot lf % 3
+        // assembled, and then to the ring slot lf % kRing
         constexpr int kPer = (kSlab + kBlock - 1) / kBlock;
         double pf[kPer];
         auto source = [&](int q) -> int64_t {     // offset within a frame, -1: outside the padded box
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble_cols(AsmArgs a)
             }
         };
         auto store = [&](int lf) {
-            double* dst = slab[lf % 3];
+            double* dst = slab[lf % kRing];
 #pragma unroll
             for (int r = 0; r < kPer; ++r) {
                 const int q = threadIdx.x + r * kBlock;
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble_cols(AsmArgs a)
             }
         };
         auto load = [&](int lf) {               // without prefetch: straight from memory to LDS
-            double* dst = slab[lf % 3];
+            double* dst = slab[lf % kRing];
             const double* fw = a.w + (int64_t)lf * s4;
             for (int q = threadIdx.x; q < kSlab; q += kBlock) {
                 const int64_t o = source(q);
@@ -297,12 +298,12 @@ __global__ __launch_bounds__(kBlock) void k_assemble_cols(AsmArgs a)
                 const int64_t p = prow * L.p1 + i;
                 const int colour = (i + j + k + l) & 1;
                 const int m = (i - 1) >> 1;
-                const double w0 = slab[l % 3][(1 * kAy + ty + 1) * kAx + tx + 1];
+                const double w0 = slab[l % kRing][(1 * kAy + ty + 1) * kAx + tx + 1];
                 const int64_t us = prow * L.rs + L.xoff + m;
                 if (colour == 0) { put<NTS>(a.ured0 + us, w0); put<NTS>(a.ured1 + us, w0); }
                 else put<NTS>(a.ublack + us, w0);
                 const double gt_here = a.G[3 * L.npad + p];
-                const int sl[3] = {(l + 2) % 3, l % 3, (l + 1) % 3};      // slots of frames l-1, l, l+1
+                const int sl[3] = {(l - 1) % kRing, l % kRing, (l + 1) % kRing};   // slots of frames l-1, l, l+1
                 assemble_cell<kSplit, NTS>(
                     a, p, i, j, k, l, colour, m,
                     [&](int di, int dj, int dk, int dl) {
@@ -316,7 +317,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble_cols(AsmArgs a)
                     acc_b, acc_r);
                 gt_below = gt_here;
             }
-            __syncthreads();             // frame l-1's slot is refilled with frame l+2 next
+            // no barrier here: the slot refilled next (frame l+2's) held frame
+            // l-2, which every wave finished reading before the barrier above
         }
     }
     assembly_decide(a, acc_b, acc_r, lds, &flag);

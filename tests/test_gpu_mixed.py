@@ -120,3 +120,39 @@ def test_mixed_passes_track_fp64_iterations(cfg1):
         assert rmx["outer"] * m <= r64["iterations"] + 2 * m, rows
         w = orc.step(n, prep["G"], w, img.centres, prep["owner"], orc.StepParams(), orc.RB)["u_resc"]
     print("step, FP64 iterations to 1e-10, mixed passes:", rows)
+
+
+def test_short_last_pass_cfg1(cfg1):
+    """SUBSURF4D_FLAG_SHORT_LAST_PASS only changes how many FP32 iterations
+    the later passes run: every step still ends with the FP64 residual at or
+    below refine_tol and within the same 1e-6 gate of the converged oracle,
+    uses at most one pass's worth of inner iterations more than the
+    fixed-length passes on any step, and over the 20 config-1 steps fewer in
+    total."""
+    img, prep, w = cfg1
+    n = img.n
+    cen, nc = B.centres_tensor(img.centres)
+    owner, G = T(prep["owner"]), T(prep["G"])
+    ws = B.alloc_workspace(n, nc, B.MIXED)
+    base = B.StepParams(precision=B.MIXED, refine_tol=1e-10, inner_sweeps=8)
+    short = B.StepParams(precision=B.MIXED, refine_tol=1e-10, inner_sweeps=8, flags=B.FLAG_SHORT_LAST_PASS)
+    tot_base = tot_short = 0
+    rows = []
+    for s in range(20):
+        ref = orc.step(n, prep["G"], w, img.centres, prep["owner"], orc.StepParams(tol=1e-14), orc.RB)
+        scale = np.abs(ref["u_resc"]).max()
+        u = T(w)
+        rb = B.step(n, 1.0, G, cen, nc, owner, u, base, ws)
+        u = T(w)
+        rs = B.step(n, 1.0, G, cen, nc, owner, u, short, ws)
+        assert rb["status"] == 0 and rs["status"] == 0
+        assert rs["rel_res"] <= 1e-10
+        e_max = np.abs(H(u) - ref["u_resc"]).max() / scale
+        assert e_max <= 1e-6, (s, e_max)
+        assert rs["iterations"] <= rb["iterations"] + 8, (s, rs, rb)
+        tot_base += rb["iterations"]
+        tot_short += rs["iterations"]
+        rows.append((s, rb["outer"], rb["iterations"], rs["outer"], rs["iterations"], float(e_max)))
+        w = ref["u_resc"]
+    print("step, passes/iterations fixed, passes/iterations shortened, max-abs rel err:", rows)
+    assert tot_short < tot_base, (tot_short, tot_base)
