@@ -30,6 +30,19 @@ def test_library_exports_every_declared_symbol():
     assert set(B.EXPORTED) == set(declared_functions())
 
 
+def test_binding_constants_match_header():
+    """Flag, status and precision values the binding passes are the header's."""
+    from paper_2111_11866_amd import binding as B
+
+    src = open(os.path.join(ROOT, "include", "subsurf4d.h")).read()
+    flags = dict(re.findall(r"#define SUBSURF4D_FLAG_([A-Z_]+) (\d+)", src))
+    assert flags, "no flags declared"
+    for name, val in flags.items():
+        assert getattr(B, "FLAG_" + name) == int(val), name
+    m = re.search(r"#define SUBSURF4D_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", src)
+    assert int(m.group(1)) << int(m.group(2)) == B.NOALLOC_SCRATCH_BYTES
+
+
 def test_host_queries():
     from paper_2111_11866_amd import binding as B
 
