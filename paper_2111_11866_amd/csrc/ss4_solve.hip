@@ -76,9 +76,19 @@ __device__ __forceinline__ void put(T* p, T v)
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
+// The t-face carried from frame to frame by a thread that marches the frames:
+// the -t face of its cell at frame l is the +t face of its cell at frame l-1,
+// whose q and 1/sqrt(eps^2 + q) were formed from the same values in the same
+// order one frame earlier.
+struct TFace {
+    double q = 0.0, rs = 0.0;
+    bool valid = false;
+};
+
 template <int MODE, bool NTS, typename WAt, typename GAt>
 __device__ __forceinline__ void assemble_cell(const AsmArgs& a, int64_t p, int i, int j, int k, int l, int colour,
-                                              int m, WAt&& wat, GAt&& gat, double& acc_b, double& acc_r)
+                                              int m, WAt&& wat, GAt&& gat, double& acc_b, double& acc_r,
+                                              TFace* tf = nullptr)
 {
     const Layout& L = a.L;
     const int64_t s1 = 1, s2 = L.p1, s3 = (int64_t)L.p1 * L.p2, s4 = s3 * L.p3;
@@ -98,9 +108,11 @@ __device__ __forceinline__ void assemble_cell(const AsmArgs& a, int64_t p, int i
     double wm[4], wp[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) { wm[d] = w1(d, -1); wp[d] = w1(d, 1); }
+    const bool carried = tf && tf->valid;            // -t face known from the previous frame
     double q[8];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
+        const bool skip_m = d == 3 && carried;
         const double gnm = (w0 - wm[d]) * a.inv_h;   // normal, -e_d face
         const double gnp = (wp[d] - w0) * a.inv_h;   // normal, +e_d face
         double qm = gnm * gnm, qp = gnp * gnp;
@@ -108,14 +120,16 @@ __device__ __forceinline__ void assemble_cell(const AsmArgs& a, int64_t p, int i
         for (int t = 0; t < 4; ++t) {
             if (t == d) continue;
             const double wpt = wp[t], wmt = wm[t];
-            const double dm_pt = w2(d, -1, t, 1), dm_mt = w2(d, -1, t, -1);
             const double dp_pt = w2(d, 1, t, 1), dp_mt = w2(d, 1, t, -1);
-            const double tm = ((dm_pt + wpt) - (dm_mt + wmt)) * (0.25 * a.inv_h);
             const double tp = ((wpt + dp_pt) - (wmt + dp_mt)) * (0.25 * a.inv_h);
-            qm += tm * tm;
             qp += tp * tp;
+            if (!skip_m) {
+                const double dm_pt = w2(d, -1, t, 1), dm_mt = w2(d, -1, t, -1);
+                const double tm = ((dm_pt + wpt) - (dm_mt + wmt)) * (0.25 * a.inv_h);
+                qm += tm * tm;
+            }
         }
-        q[2 * d] = qm;
+        q[2 * d] = skip_m ? tf->q : qm;
         q[2 * d + 1] = qp;
     }
     double qs = 0.0;
@@ -131,8 +145,15 @@ __device__ __forceinline__ void assemble_cell(const AsmArgs& a, int64_t p, int i
         // G/A as a product with the reciprocal square root (a few ulps from
         // the quotient by the rounded root, at a third of the instructions;
         // the batched assembly forms it the same way)
-        c[2 * d] = scale * gm * rsqrt(a.eps2 + q[2 * d]);
-        c[2 * d + 1] = scale * gp * rsqrt(a.eps2 + q[2 * d + 1]);
+        const double rm = (d == 3 && carried) ? tf->rs : rsqrt(a.eps2 + q[2 * d]);
+        const double rp = rsqrt(a.eps2 + q[2 * d + 1]);
+        c[2 * d] = scale * gm * rm;
+        c[2 * d + 1] = scale * gp * rp;
+        if (d == 3 && tf) {
+            tf->q = q[7];
+            tf->rs = rp;
+            tf->valid = true;
+        }
     }
     double D = 1.0;
 #pragma unroll
@@ -292,6 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble_cols(AsmArgs a)
         load(1);
         if (PREFETCH) fetch(2);
         double gt_below = active ? a.G[3 * L.npad + ((int64_t)k * L.p2 + j) * L.p1 + i] : 0.0;   // G_t of frame 0
+        TFace tface;                     // the +t face of the previous frame's cell
         for (int l = 1; l <= L.n4; ++l) {
             if (PREFETCH) store(l + 1);
             else load(l + 1);
@@ -318,7 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble_cols(AsmArgs a)
                         const int64_t o = d == 0 ? 1 : (d == 1 ? s2 : s3);
                         return a.G[(int64_t)d * L.npad + p - (plus ? 0 : o)];
                     },
-                    acc_b, acc_r);
+                    acc_b, acc_r, &tface);
                 gt_below = gt_here;
             }
             // no barrier here: the slot refilled next (frame l+2's) held frame
