@@ -469,7 +469,13 @@ __global__ __launch_bounds__(kBlock) void k_face_g(Layout L, uint64_t mp1, uint6
     using IDX = typename std::conditional<NARROW, uint32_t, int64_t>::type;
     const int n[4] = {L.n1, L.n2, L.n3, L.n4};
     const IDX stride[4] = {1, (IDX)L.n1, (IDX)L.n1 * (IDX)L.n2, (IDX)L.n1 * (IDX)L.n2 * (IDX)L.n3};
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < L.npad; p += (int64_t)gridDim.x * blockDim.x) {
+    // chunks of kBlock cells dealt XCD-contiguously: the rows around a chunk
+    // (y, z neighbours of both images) are read by blocks of the same XCD at
+    // about the same time, so they come from its L2
+    const int64_t nchunk = (L.npad + kBlock - 1) / kBlock;
+    for (TileWalk tw(nchunk); tw.t < tw.end; tw.t += tw.step) {
+        const int64_t p = tw.t * kBlock + threadIdx.x;
+        if (p >= L.npad) continue;
         int c[4];
         if (NARROW) {
             const uint32_t pp = (uint32_t)p;
