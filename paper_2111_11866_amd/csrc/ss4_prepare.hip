@@ -319,7 +319,12 @@ __global__ __launch_bounds__(kBlock) void k_lhe_sweep(Layout L, HeatDiv M, doubl
     const double* __restrict__ O = J + (1 - COLOR) * ncq;   // the other colour: read only
     double* __restrict__ W = J + COLOR * ncq;               // this colour: updated
     double acc = 0.0;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < ncq2; g += (int64_t)gridDim.x * blockDim.x) {
+    // chunks of kBlock slots dealt XCD-contiguously, so the y and z
+    // neighbour rows of a chunk are read by blocks of the same XCD (its L2)
+    const int64_t nch = (ncq2 + kBlock - 1) / kBlock;
+    for (TileWalk tw(nch); tw.t < tw.end; tw.t += tw.step) {
+        const int64_t g = tw.t * kBlock + threadIdx.x;
+        if (g >= ncq2) continue;
         int m, j, k;
         if (NARROW) {
             const uint32_t gg = (uint32_t)g;
@@ -404,7 +409,10 @@ __global__ __launch_bounds__(kBlock) void k_lhe_residual(Layout L, HeatDiv M, do
     if (C->done) return;
     const int64_t sy = L.n1, sz = (int64_t)L.n1 * L.n2, st = sz * L.n3;
     double ar = 0.0, ab = 0.0;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < L.nint; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t nch = (L.nint + kBlock - 1) / kBlock;      // chunks dealt XCD-contiguously
+    for (TileWalk tw(nch); tw.t < tw.end; tw.t += tw.step) {
+        const int64_t q = tw.t * kBlock + threadIdx.x;
+        if (q >= L.nint) continue;
         int i, j, kk, l;
         if (NARROW) {
             const uint32_t qq = (uint32_t)q;
