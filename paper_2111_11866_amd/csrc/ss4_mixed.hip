@@ -278,7 +278,9 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
     // for the FP32 correction, in two designs (3.36 vs 4.13 TB/s on the
     // 512x512x96x16 volume; a tile-per-wave form with contiguous 2 KB record
     // runs and 8-byte d accesses, same bits: 165.7 vs 162.1 ms per step)
-    const int res_g = resident_grid(reinterpret_cast<const void*>(&k_mx_sweep<0, false>)) / 2;
+    int res_g = (int)((int64_t)resident_grid(reinterpret_cast<const void*>(&k_mx_sweep<0, false>)) *
+                      sweep_grid_percent() / 100);
+    if (res_g > kGridCap) res_g = kGridCap;   // the per-block partial arrays hold kGridCap entries
     const int grid_cols = (int)(((ncol < res_g ? ncol : res_g) + kXcd - 1) / kXcd * kXcd);
 
     auto enqueue_sweeps = [&](int mm) {

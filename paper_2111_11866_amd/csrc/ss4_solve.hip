@@ -544,16 +544,6 @@ __global__ void k_write_result(const Ctrl* C, subsurf4d_result* res, int sweeps_
     }
 }
 
-// SUBSURF4D_SWEEP_GRID=<percent> sizes the two-cell sweeps' grids as that
-// share of the resident grid (default 50); the tile walk gives the same
-// iterate for any grid.
-int sweep_grid_percent()
-{
-    const char* env = getenv("SUBSURF4D_SWEEP_GRID");
-    const int pc = env ? atoi(env) : 50;
-    return pc < 1 ? 1 : (pc > 400 ? 400 : pc);
-}
-
 int sweep_grid(const Layout& L, int variant)
 {
     int64_t work;
@@ -910,6 +900,16 @@ int run_solve(const WsPlan& P, const double* coef, const double* b, double* u,
     }
     SS4_HIP(hipStreamSynchronize(s));
     return res ? res->status : 0;
+}
+
+// SUBSURF4D_SWEEP_GRID=<percent> sizes the grids of the frame-marching FP64
+// and FP32 sweeps as that share of the resident grid (default 50); the tile
+// walk gives the same iterate for any grid.
+int sweep_grid_percent()
+{
+    const char* env = getenv("SUBSURF4D_SWEEP_GRID");
+    const int pc = env ? atoi(env) : 50;
+    return pc < 1 ? 1 : (pc > 400 ? 400 : pc);
 }
 
 }  // namespace ss4
