@@ -53,8 +53,8 @@ int hip_fail(hipError_t e, const char* what);
 // grid-stride kernel never runs a partial second round of blocks.
 int resident_grid(const void* kernel);
 int resident_grid_bs(const void* kernel, int block);   // the same for blocks of `block` threads
-// SUBSURF4D_SWEEP_GRID (percent of the resident grid, default 50), read per solve
-int sweep_grid_percent();
+// SUBSURF4D_SWEEP_GRID (percent of the resident grid, else dflt), read per solve
+int sweep_grid_percent(int dflt);
 
 // preparation (prepare.hip)
 int run_prepare(const WsPlan& P, double h, const void* image, int dtype,

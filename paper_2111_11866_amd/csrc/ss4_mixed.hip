@@ -278,8 +278,12 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
     // for the FP32 correction, in two designs (3.36 vs 4.13 TB/s on the
     // 512x512x96x16 volume; a tile-per-wave form with contiguous 2 KB record
     // runs and 8-byte d accesses, same bits: 165.7 vs 162.1 ms per step)
+    // three quarters of the resident grid: on the 512x512x96x16 volume the
+    // concurrent window of an XCD is then 48 z-planes x 4 slot tiles, half a
+    // row of tiles (1.493 ms per half-sweep against 1.535 at one half, 1.52-1.68
+    // at 60-125% except 150%, 1.507, a whole row); same iterate for any grid
     int res_g = (int)((int64_t)resident_grid(reinterpret_cast<const void*>(&k_mx_sweep<0, false>)) *
-                      sweep_grid_percent() / 100);
+                      sweep_grid_percent(75) / 100);
     if (res_g > kGridCap) res_g = kGridCap;   // the per-block partial arrays hold kGridCap entries
     const int grid_cols = (int)(((ncol < res_g ? ncol : res_g) + kXcd - 1) / kXcd * kXcd);
 

@@ -550,7 +550,7 @@ int sweep_grid(const Layout& L, int variant)
     int res;
     if (variant == 2) {
         work = (int64_t)L.ntm * ((L.n2 + 3) >> 2) * L.n3;
-        res = (int)((int64_t)resident_grid(reinterpret_cast<const void*>(&k_sweep_t2<0>)) * sweep_grid_percent() / 100);
+        res = (int)((int64_t)resident_grid(reinterpret_cast<const void*>(&k_sweep_t2<0>)) * sweep_grid_percent(50) / 100);
         if (res > kGridCap) res = kGridCap;    // the per-block partial arrays hold kGridCap entries
         const int64_t g = work < res ? work : res;
         return (int)((g + kXcd - 1) / kXcd * kXcd);
@@ -903,12 +903,12 @@ int run_solve(const WsPlan& P, const double* coef, const double* b, double* u,
 }
 
 // SUBSURF4D_SWEEP_GRID=<percent> sizes the grids of the frame-marching FP64
-// and FP32 sweeps as that share of the resident grid (default 50); the tile
-// walk gives the same iterate for any grid.
-int sweep_grid_percent()
+// and FP32 sweeps as that share of the resident grid (defaults: the caller's
+// `dflt`); the tile walk gives the same iterate for any grid.
+int sweep_grid_percent(int dflt)
 {
     const char* env = getenv("SUBSURF4D_SWEEP_GRID");
-    const int pc = env ? atoi(env) : 50;
+    const int pc = env ? atoi(env) : dflt;
     return pc < 1 ? 1 : (pc > 400 ? 400 : pc);
 }
 
