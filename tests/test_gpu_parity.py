@@ -574,3 +574,52 @@ def test_checkpoint_resume_bit_identical(cfg1, tmp_path):
     for _ in range(10):
         resumed.step(sp)
     assert torch.equal(resumed.u, full.u)
+
+
+def test_sweep_forms_and_grids_give_the_same_bits(monkeypatch):
+    """Every red-black sweep form (row tiles, one-cell and two-cell frame
+    marching, 8-row blocks), every grid size of the frame-marching sweeps and
+    both assembly loadings and store kinds leave the same iterate, bit for
+    bit: red-black SOR does not depend on the order of updates within a
+    colour, the fixed-count solve tests no stopping rule, and each cell's
+    arithmetic is the same in every form.  Also the mixed step at several
+    grids of its FP32 sweep: same iterate, passes and inner iterations."""
+    n = (131, 10, 6, 4)                   # two-cell rows (>= 64 slots), ragged in every axis
+    rng = np.random.default_rng(77)
+    G = T(rng.uniform(0.05, 1.0, size=(4,) + B.padded_shape(n)))
+    w = np.zeros(B.padded_shape(n))
+    w[1:-1, 1:-1, 1:-1, 1:-1] = rng.uniform(0.0, 1.0, size=B.interior_shape(n))
+    ws = B.alloc_workspace(n, 0, B.MIXED)
+    sp = B.StepParams(fixed_iters=9, rescale=False, omega=1.7)
+    forms = [{}, {"SUBSURF4D_SWEEP": "r"}, {"SUBSURF4D_SWEEP": "t"}, {"SUBSURF4D_SWEEP": "8"},
+             {"SUBSURF4D_SWEEP_GRID": "13"}, {"SUBSURF4D_SWEEP_GRID": "100"}, {"SUBSURF4D_SWEEP_GRID": "300"},
+             {"SUBSURF4D_ASM_PREFETCH": "0"}, {"SUBSURF4D_ASM_NT": "0"}]
+    keys = {k for f in forms for k in f}
+    ref = None
+    for f in forms:
+        for k in keys:
+            monkeypatch.delenv(k, raising=False)
+        for k, v in f.items():
+            monkeypatch.setenv(k, v)
+        u, r = step_gpu(n, G, w, None, 0, None, sp, ws)
+        assert r["iterations"] == 9, (f, r)
+        if ref is None:
+            ref = u
+        else:
+            assert np.array_equal(u, ref), f
+    for k in keys:
+        monkeypatch.delenv(k, raising=False)
+    msp = B.StepParams(precision=B.MIXED, rescale=False, refine_tol=1e-11, inner_sweeps=6, omega=1.7)
+    mref = None
+    for g in (None, "20", "75", "250"):
+        if g is None:
+            monkeypatch.delenv("SUBSURF4D_SWEEP_GRID", raising=False)
+        else:
+            monkeypatch.setenv("SUBSURF4D_SWEEP_GRID", g)
+        u, r = step_gpu(n, G, w, None, 0, None, msp, ws)
+        assert r["status"] == 0
+        if mref is None:
+            mref = (u, r["outer"], r["iterations"])
+        else:
+            assert np.array_equal(u, mref[0]) and r["outer"] == mref[1] and r["iterations"] == mref[2], g
+    monkeypatch.delenv("SUBSURF4D_SWEEP_GRID", raising=False)
