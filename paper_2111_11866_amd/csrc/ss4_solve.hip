@@ -555,6 +555,16 @@ int sweep_grid(const Layout& L, int variant)
         const int64_t g = work < res ? work : res;
         return (int)((g + kXcd - 1) / kXcd * kXcd);
     }
+    if (variant == 5) {
+        // 64 KB of LDS per block: two blocks per CU at the resident size, the
+        // occupancy the immediate-store form has at half its resident grid
+        work = (int64_t)L.ntm * ((L.n2 + 3) >> 2) * L.n3;
+        res = (int)((int64_t)resident_grid(reinterpret_cast<const void*>(&k_sweep_t2<0, 4, 16>)) *
+                    sweep_grid_percent(100) / 100);
+        if (res > kGridCap) res = kGridCap;
+        const int64_t g = work < res ? work : res;
+        return (int)((g + kXcd - 1) / kXcd * kXcd);
+    }
     if (variant == 3) {
         work = (int64_t)L.ntm * ((L.n2 + 7) >> 3) * L.n3;
         res = resident_grid_bs(reinterpret_cast<const void*>(&k_sweep_t2<0, 8>), 512) / 2;
@@ -575,12 +585,15 @@ int sweep_grid(const Layout& L, int variant)
     return (int)((g + kXcd - 1) / kXcd * kXcd);
 }
 
-// Sweep kernel choice.  2 (default for rows of >= 64 slots): frame-marching
-// with two cells per lane and 16-byte accesses (k_sweep_t2), the fastest
-// measured on the 512x512x96x16 volume (3.95 ms vs 4.22 ms per half-sweep);
-// 1 (default for narrower rows): frame-marching, one cell per lane
-// (k_sweep_tm); 0: row tiles (k_sweep).  SUBSURF4D_SWEEP=r|t|p selects one
-// explicitly (all three give the same iterates).
+// Sweep kernel choice.  5 (default for rows of >= 64 slots): frame-marching
+// with two cells per lane and 16-byte accesses (k_sweep_t2), new values held
+// in LDS and written after a block barrier every 16 frames, the fastest
+// measured on the 512x512x96x16 volume (3.785 ms per half-sweep against
+// 3.954 storing each frame at once, 4.22 with one cell per lane); 2: the
+// same storing at once; 1 (default for narrower rows): frame-marching, one
+// cell per lane (k_sweep_tm); 0: row tiles (k_sweep); 3: two cells per lane,
+// 8-row blocks.  SUBSURF4D_SWEEP=r|t|p|8 selects one explicitly (all give the
+// same iterates).
 int sweep_variant(const Layout& L)
 {
     const bool wide = L.half >= 64;   // 128-byte aligned u rows, pairs stay in the row
@@ -590,7 +603,11 @@ int sweep_variant(const Layout& L)
     // 3: the two-cell form with 8 y-rows per block (fewer neighbour rows
     // outside each column tile); SUBSURF4D_SWEEP=8 selects it
     if (env && env[0] == '8') return wide ? 3 : 1;
-    return wide ? 2 : 1;
+    // 2: the two-cell form storing each frame's new values at once (SUBSURF4D_SWEEP=p)
+    if (env && env[0] == 'p') return wide ? 2 : 1;
+    // 5 (default for rows of >= 64 slots): the two-cell form with a column's
+    // new values held in LDS and written after a block barrier every 16 frames
+    return wide ? 5 : 1;
 }
 
 void fill_result(const Ctrl& hc, subsurf4d_result* res)
@@ -648,14 +665,16 @@ int run_sor_loop(const WsPlan& P, const subsurf4d_step_params& sp, void* ws, hip
         red.uin = ured[(k - 1) & 1];
         red.uout = ured[k & 1];
         red.check = (k >= 2) && (((k - 1) % check_every == 0) || (k - 1 >= max_iter));
-        if (variant == 3) k_sweep_t2<0, 8><<<grid, 512, 0, s>>>(red);
+        if (variant == 5) k_sweep_t2<0, 4, 16><<<grid, kBlock, 0, s>>>(red);
+        else if (variant == 3) k_sweep_t2<0, 8><<<grid, 512, 0, s>>>(red);
         else if (variant == 2) k_sweep_t2<0><<<grid, kBlock, 0, s>>>(red);
         else if (variant == 1) k_sweep_tm<0><<<grid, kBlock, 0, s>>>(red);
         else k_sweep<0><<<grid, kBlock, 0, s>>>(red);
         if (k <= max_iter) {
             black.k = k;
             black.uoth = ured[k & 1];
-            if (variant == 3) k_sweep_t2<1, 8><<<grid, 512, 0, s>>>(black);
+            if (variant == 5) k_sweep_t2<1, 4, 16><<<grid, kBlock, 0, s>>>(black);
+            else if (variant == 3) k_sweep_t2<1, 8><<<grid, 512, 0, s>>>(black);
             else if (variant == 2) k_sweep_t2<1><<<grid, kBlock, 0, s>>>(black);
             else if (variant == 1) k_sweep_tm<1><<<grid, kBlock, 0, s>>>(black);
             else k_sweep<1><<<grid, kBlock, 0, s>>>(black);

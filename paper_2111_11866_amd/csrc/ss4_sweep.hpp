@@ -266,11 +266,17 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tm(SweepArgs a)
 // bytes per lane.  A block of NW waves walks column tiles (128 slots x NW
 // y-rows at one z), marching over the frames of each; tiles are dealt as for
 // k_sweep_tm.
-template <int COLOR, int NW = 4>
+// DF > 0: a thread's new values of up to DF frames wait in LDS and are
+// written after a block barrier, so the block's waves write together: the
+// write stream then interleaves less with the reads of the other blocks.
+template <int COLOR, int NW = 4, int DF = 0>
 __global__ __launch_bounds__(64 * NW) void k_sweep_t2(SweepArgs a)
 {
+    constexpr bool DEFER = DF > 0;
+    constexpr int kDeferFrames = DEFER ? DF : 1;
     __shared__ double lds[NW];
     __shared__ int flag;
+    __shared__ dvec2 obuf[kDeferFrames][DEFER ? 64 * NW : 1];
     Ctrl* C = a.C;
     if (C->done) return;
     const Layout& L = a.L;
@@ -335,7 +341,10 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_t2(SweepArgs a)
                     const double ub0 = s0 / D0, ub1 = s1 / D1;
                     const double n0 = om * ub0 + om1 * uold.x;
                     const double n1 = om * ub1 + om1 * uold.y;
-                    if (a1) {
+                    if (DEFER) {
+                        const dvec2 nv = {n0, n1};
+                        obuf[(l - 1) % kDeferFrames][threadIdx.x] = nv;
+                    } else if (a1) {
                         const dvec2 nv = {n0, n1};
                         st2_stream(a.uout + ui, nv);
                     } else {
@@ -349,6 +358,22 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_t2(SweepArgs a)
             }
             Bm = Bc;
             Bc = Bp;
+            if (DEFER && (l % kDeferFrames == 0 || l == L.n4)) {
+                // the same l and N4 in every wave: a uniform barrier
+                __syncthreads();
+                if (jok) {
+                    const int l0 = (l - 1) / kDeferFrames * kDeferFrames + 1;
+                    for (int lf = l0; lf <= l; ++lf) {
+                        const int parf = (COLOR + j + k + lf) & 1;
+                        const int cntf = parf ? (L.n1 + 1) >> 1 : L.n1 >> 1;
+                        if (m >= cntf) continue;
+                        const dvec2 nv = obuf[(lf - 1) % kDeferFrames][threadIdx.x];
+                        double* dst = a.uout + ub + (int64_t)lf * st;
+                        if (m + 1 < cntf) st2_stream(dst, nv);
+                        else st_stream(dst, nv.x);
+                    }
+                }
+            }
         }
     }
     finish_sweep<COLOR, NW>(a, acc, lds, &flag);
