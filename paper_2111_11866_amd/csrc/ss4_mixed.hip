@@ -138,13 +138,9 @@ __device__ __forceinline__ float mx_cell(uint4 w, float rhs, float xl, float xr,
 // reads) and its black half-sweep takes the old d as 0 without reading it;
 // both give the bits of the general form on a zero d, so no pass needs d
 // cleared beforehand.
-// DF > 0: the new corrections of up to DF frames wait in LDS and are written
-// after a block barrier (the block's waves write together, as in the FP64 sweep).
-template <int COLOR, bool FIRST, int DF = 0>
+template <int COLOR, bool FIRST>
 __global__ __launch_bounds__(kBlock) void k_mx_sweep(MxArgs a)
 {
-    constexpr bool DEFER = DF > 0;
-    __shared__ float obuf[DEFER ? DF : 1][DEFER ? kBlock : 1];
     if (a.C->done) return;
     const Layout& L = a.L;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -195,27 +191,12 @@ __global__ __launch_bounds__(kBlock) void k_mx_sweep(MxArgs a)
                     const int64_t q = mrec(L, COLOR, rb + (int64_t)(l - 1) * L.n3 * L.n2, m);
                     const uint4 w = ld16_stream(a.c16 + q);
                     const float rhs = __builtin_nontemporal_load(a.rf + q);
-                    const float v = mx_cell(w, rhs, par ? left : Bc, par ? Bc : right, oth[ui - sy], oth[ui + sy],
-                                            oth[ui - sz], oth[ui + sz], Bm, Bp, om, om1, FIRST ? 0.0f : own[ui]);
-                    if constexpr (DEFER) obuf[(l - 1) % DF][threadIdx.x] = v;
-                    else own[ui] = v;
+                    own[ui] = mx_cell(w, rhs, par ? left : Bc, par ? Bc : right, oth[ui - sy], oth[ui + sy],
+                                      oth[ui - sz], oth[ui + sz], Bm, Bp, om, om1, FIRST ? 0.0f : own[ui]);
                 }
             }
             Bm = Bc;
             Bc = Bp;
-            if constexpr (DEFER) {
-                if (l % DF == 0 || l == L.n4) {
-                    __syncthreads();              // uniform: the same l and N4 in every wave
-                    if (jok) {
-                        const int l0 = (l - 1) / DF * DF + 1;
-                        for (int lf = l0; lf <= l; ++lf) {
-                            const int parf = (COLOR + j + k + lf) & 1;
-                            if (m < (parf ? (L.n1 + 1) >> 1 : L.n1 >> 1))
-                                own[ub + (int64_t)lf * st] = obuf[(lf - 1) % DF][threadIdx.x];
-                        }
-                    }
-                }
-            }
         }
     }
 }
@@ -306,18 +287,7 @@ int run_mixed_solve(const WsPlan& P, double h, const double* G, const double* w,
     if (res_g > kGridCap) res_g = kGridCap;   // the per-block partial arrays hold kGridCap entries
     const int grid_cols = (int)(((ncol < res_g ? ncol : res_g) + kXcd - 1) / kXcd * kXcd);
 
-    const char* env_def = getenv("SUBSURF4D_MX_DEFER");
-    const bool mx_defer = env_def && env_def[0] == '1';
     auto enqueue_sweeps = [&](int mm) {
-        if (mx_defer) {
-            k_mx_sweep<0, true><<<grid_cols, kBlock, 0, s>>>(a);
-            k_mx_sweep<1, true, 16><<<grid_cols, kBlock, 0, s>>>(a);
-            for (int it = 1; it < mm; ++it) {
-                k_mx_sweep<0, false, 16><<<grid_cols, kBlock, 0, s>>>(a);
-                k_mx_sweep<1, false, 16><<<grid_cols, kBlock, 0, s>>>(a);
-            }
-            return;
-        }
         k_mx_sweep<0, true><<<grid_cols, kBlock, 0, s>>>(a);
         k_mx_sweep<1, true><<<grid_cols, kBlock, 0, s>>>(a);
         for (int it = 1; it < mm; ++it) {
