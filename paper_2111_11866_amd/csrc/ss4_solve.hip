@@ -565,6 +565,17 @@ int sweep_grid(const Layout& L, int variant)
         const int64_t g = work < res ? work : res;
         return (int)((g + kXcd - 1) / kXcd * kXcd);
     }
+    if (variant == 7 || variant == 9) {
+        // 128 KB of LDS per block: one block per CU at the resident size
+        const int rows = variant == 9 ? 16 : 8;
+        work = (int64_t)L.ntm * ((L.n2 + rows - 1) / rows) * L.n3;
+        const void* kern = variant == 7 ? reinterpret_cast<const void*>(&k_sweep_t2<0, 8, 16>)
+                                        : reinterpret_cast<const void*>(&k_sweep_t2<0, 16, 8>);
+        res = (int)((int64_t)resident_grid_bs(kern, 64 * rows) * sweep_grid_percent(100) / 100);
+        if (res > kGridCap) res = kGridCap;
+        const int64_t g = work < res ? work : res;
+        return (int)((g + kXcd - 1) / kXcd * kXcd);
+    }
     if (variant == 3) {
         work = (int64_t)L.ntm * ((L.n2 + 7) >> 3) * L.n3;
         res = resident_grid_bs(reinterpret_cast<const void*>(&k_sweep_t2<0, 8>), 512) / 2;
@@ -585,15 +596,16 @@ int sweep_grid(const Layout& L, int variant)
     return (int)((g + kXcd - 1) / kXcd * kXcd);
 }
 
-// Sweep kernel choice.  5 (default for rows of >= 64 slots): frame-marching
-// with two cells per lane and 16-byte accesses (k_sweep_t2), new values held
-// in LDS and written after a block barrier every 16 frames, the fastest
-// measured on the 512x512x96x16 volume (3.785 ms per half-sweep against
-// 3.954 storing each frame at once, 4.22 with one cell per lane); 2: the
-// same storing at once; 1 (default for narrower rows): frame-marching, one
-// cell per lane (k_sweep_tm); 0: row tiles (k_sweep); 3: two cells per lane,
-// 8-row blocks.  SUBSURF4D_SWEEP=r|t|p|8 selects one explicitly (all give the
-// same iterates).
+// Sweep kernel choice.  9 (default for rows of >= 64 slots): frame-marching
+// with two cells per lane and 16-byte accesses (k_sweep_t2) in 16-row blocks,
+// new values held in LDS and written after a block barrier every 8 frames,
+// the fastest measured on the 512x512x96x16 volume (3.566 ms per half-sweep;
+// 3.603 with 8-row blocks and 16 frames (7), 3.785 with 4-row blocks and 16
+// frames (5), 3.954 storing each frame at once (2), 4.22 with one cell per
+// lane); 1 (default for narrower rows): frame-marching, one cell per lane
+// (k_sweep_tm); 0: row tiles (k_sweep); 3: two cells per lane, 8-row blocks,
+// storing at once.  SUBSURF4D_SWEEP=r|t|p|8|d|D selects one explicitly (all
+// give the same iterates).
 int sweep_variant(const Layout& L)
 {
     const bool wide = L.half >= 64;   // 128-byte aligned u rows, pairs stay in the row
@@ -605,9 +617,14 @@ int sweep_variant(const Layout& L)
     if (env && env[0] == '8') return wide ? 3 : 1;
     // 2: the two-cell form storing each frame's new values at once (SUBSURF4D_SWEEP=p)
     if (env && env[0] == 'p') return wide ? 2 : 1;
-    // 5 (default for rows of >= 64 slots): the two-cell form with a column's
-    // new values held in LDS and written after a block barrier every 16 frames
-    return wide ? 5 : 1;
+    // 5: 4-row blocks with the deferred writes, 16 frames (SUBSURF4D_SWEEP=d);
+    // 7: 8-row blocks, 16 frames (SUBSURF4D_SWEEP=D)
+    if (env && env[0] == 'd') return wide ? 5 : 1;
+    if (env && env[0] == 'D') return wide ? 7 : 1;
+    // 9 (default for rows of >= 64 slots): the two-cell form in 16-row blocks
+    // of 1024 threads, new values held in LDS (128 KB) and written after a
+    // block barrier every 8 frames
+    return wide ? 9 : 1;
 }
 
 void fill_result(const Ctrl& hc, subsurf4d_result* res)
@@ -666,6 +683,8 @@ int run_sor_loop(const WsPlan& P, const subsurf4d_step_params& sp, void* ws, hip
         red.uout = ured[k & 1];
         red.check = (k >= 2) && (((k - 1) % check_every == 0) || (k - 1 >= max_iter));
         if (variant == 5) k_sweep_t2<0, 4, 16><<<grid, kBlock, 0, s>>>(red);
+        else if (variant == 7) k_sweep_t2<0, 8, 16><<<grid, 512, 0, s>>>(red);
+        else if (variant == 9) k_sweep_t2<0, 16, 8><<<grid, 1024, 0, s>>>(red);
         else if (variant == 3) k_sweep_t2<0, 8><<<grid, 512, 0, s>>>(red);
         else if (variant == 2) k_sweep_t2<0><<<grid, kBlock, 0, s>>>(red);
         else if (variant == 1) k_sweep_tm<0><<<grid, kBlock, 0, s>>>(red);
@@ -674,6 +693,8 @@ int run_sor_loop(const WsPlan& P, const subsurf4d_step_params& sp, void* ws, hip
             black.k = k;
             black.uoth = ured[k & 1];
             if (variant == 5) k_sweep_t2<1, 4, 16><<<grid, kBlock, 0, s>>>(black);
+            else if (variant == 7) k_sweep_t2<1, 8, 16><<<grid, 512, 0, s>>>(black);
+            else if (variant == 9) k_sweep_t2<1, 16, 8><<<grid, 1024, 0, s>>>(black);
             else if (variant == 3) k_sweep_t2<1, 8><<<grid, 512, 0, s>>>(black);
             else if (variant == 2) k_sweep_t2<1><<<grid, kBlock, 0, s>>>(black);
             else if (variant == 1) k_sweep_tm<1><<<grid, kBlock, 0, s>>>(black);

@@ -592,7 +592,7 @@ def test_sweep_forms_and_grids_give_the_same_bits(monkeypatch):
     ws = B.alloc_workspace(n, 0, B.MIXED)
     sp = B.StepParams(fixed_iters=9, rescale=False, omega=1.7)
     forms = [{}, {"SUBSURF4D_SWEEP": "r"}, {"SUBSURF4D_SWEEP": "t"}, {"SUBSURF4D_SWEEP": "8"},
-             {"SUBSURF4D_SWEEP": "p"},
+             {"SUBSURF4D_SWEEP": "p"}, {"SUBSURF4D_SWEEP": "d"}, {"SUBSURF4D_SWEEP": "D"},
              {"SUBSURF4D_SWEEP_GRID": "13"}, {"SUBSURF4D_SWEEP_GRID": "100"}, {"SUBSURF4D_SWEEP_GRID": "300"},
              {"SUBSURF4D_ASM_PREFETCH": "0"}, {"SUBSURF4D_ASM_NT": "0"}]
     keys = {k for f in forms for k in f}
