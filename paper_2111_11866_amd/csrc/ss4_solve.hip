@@ -326,7 +326,10 @@ __global__ __launch_bounds__(kBlock) void k_assemble_cols(AsmArgs a)
                 const int m = (i - 1) >> 1;
                 const double w0 = slab[l % kRing][(1 * kAy + ty + 1) * kAx + tx + 1];
                 const int64_t us = prow * L.rs + L.xoff + m;
-                if (colour == 0) { put<NTS>(a.ured0 + us, w0); put<NTS>(a.ured1 + us, w0); }
+                // the red value goes to the first ping-pong buffer only: the
+                // first red half-sweep writes every interior cell of the second
+                // before anything reads it
+                if (colour == 0) put<NTS>(a.ured0 + us, w0);
                 else put<NTS>(a.ublack + us, w0);
                 const double gt_here = a.G[3 * L.npad + p];
                 const int sl[3] = {(l - 1) % kRing, l % kRing, (l + 1) % kRing};   // slots of frames l-1, l, l+1
