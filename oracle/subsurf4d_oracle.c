@@ -417,11 +417,7 @@ void oracle_init_u(const int *n, const oracle_centre *cs, int nc, double v, doub
                     for (int m = 0; m < nc; ++m) {
                         if (cs[m].frame != l - 1) continue;
                         const double dd = sqrt(dist2(&cs[m], i, j, k));
-                        double val = 1.0 / (dd + v);
-                        if (R > 0.0) {
-                            val = val - 1.0 / (R + v);
-                            if (val < 0.0) val = 0.0;
-                        }
+                        const double val = 1.0 / (dd + v);
                         if (!any || val > best) best = val;
                         any = 1;
                     }

@@ -51,7 +51,7 @@ MUTANTS = {
     "normal_t_2h": ("if (t == d) { g[t] = (vQ - vP) / h; continue; }",
                     "if (t == d) { g[t] = (vQ - vP) / (t==3 ? 2*h : h); continue; }"),
     # initial function without the cut-off shift 1/(R+v)
-    "init_no_shift": ("val = val - 1.0 / (R + v);", "val = val - 0.0 / (R + v);"),
+    "init_no_shift": ("double val = 1.0 / (dd + v) - 1.0 / (R + v);", "double val = 1.0 / (dd + v) - 0.0 / (R + v);"),
 }
 
 
