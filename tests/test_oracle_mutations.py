@@ -1,6 +1,7 @@
 """The oracle's pins have teeth: each plausible mistake below, planted in a
 temporary copy of the oracle's C source (never in the oracle itself), makes
-at least one test of tests/test_oracle_pins.py fail.
+at least one test of tests/test_oracle_pins.py (tests/test_oracle_tracking.py
+for the cell tracking) fail.
 
 Slow (every mutant is compiled and the pins run against it): set
 SUBSURF4D_SLOW=1 to run it.  CPU only.
@@ -15,7 +16,10 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "subsurf4d_oracle.c")
 
-# name: (text of the oracle, mistaken text)
+PINS = os.path.join(ROOT, "tests", "test_oracle_pins.py")
+TRACKING = os.path.join(ROOT, "tests", "test_oracle_tracking.py")
+
+# name: (text of the oracle, mistaken text[, the test file whose pins must catch it])
 MUTANTS = {
     # G on the "-e_d" face taken from the cell itself instead of P - e_d
     "minus_face_G_from_P": ("Gf[2 * d] = G[(size_t)d * np + pidx(n, Pm[0], Pm[1], Pm[2], Pm[3])];",
@@ -52,6 +56,17 @@ MUTANTS = {
                     "if (t == d) { g[t] = (vQ - vP) / (t==3 ? 2*h : h); continue; }"),
     # initial function without the cut-off shift 1/(R+v)
     "init_no_shift": ("double val = 1.0 / (dd + v) - 1.0 / (R + v);", "double val = 1.0 / (dd + v) - 0.0 / (R + v);"),
+    # stopping rule against the absolute residual instead of tol * ||b||
+    "stop_absolute": ("if (R <= tol * bn) return 0;", "if (R <= tol) return 0;"),
+    # cell tracking: one face neighbour (+z) missing from the flood fill
+    "label_no_plus_z": ("{ci, cj, ck - 1}, {ci, cj, ck + 1}};", "{ci, cj, ck - 1}, {ci, cj, ck - 1}};", TRACKING),
+    # distances: the region outside the image not counted as outside
+    "dist_no_outer_shell": ("for (long c = 0; c <= n[2] + 1; ++c)", "for (long c = 1; c <= n[2]; ++c)", TRACKING),
+    # distances: the z offset not squared
+    "dist_z_not_squared": ("+ (c - k) * (c - k);", "+ (c - k);", TRACKING),
+    # backward link looked up in the cell's own frame instead of frame l-1
+    "link_same_frame": ("const int32_t below = label[(size_t)r[2] - fsz];", "const int32_t below = label[(size_t)r[2]];",
+                        TRACKING),
 }
 
 
@@ -61,7 +76,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     gcc = shutil.which("gcc")
     if gcc is None:
         pytest.skip("gcc is missing")
-    good, bad = MUTANTS[name]
+    good, bad, pins = (MUTANTS[name] + (PINS,))[:3]
     src = open(SRC).read()
     assert src.count(good) >= 1, f"{name}: the oracle text it mutates has changed"
     mutant = tmp_path / "mutant.c"
@@ -71,7 +86,8 @@ def test_pins_catch_planted_mistake(name, tmp_path):
                     str(mutant), "-lm"], check=True)
     env = dict(os.environ, SUBSURF4D_ORACLE_LIB=str(lib))
     env.pop("SUBSURF4D_SLOW", None)
-    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-q", "-x",
+    r = subprocess.run([sys.executable, "-m", "pytest", pins, "-q", "-x",
                         "-m", "not gpu", "-p", "no:cacheprovider"], cwd=ROOT, env=env, capture_output=True, text=True,
                        timeout=600)
-    assert r.returncode != 0, f"{name}: no pin failed\n{r.stdout[-2000:]}"
+    # exit status 1 with a failed test: a pin caught it (not a load or collection error)
+    assert r.returncode == 1 and " failed" in r.stdout, f"{name}: no pin failed\n{r.stdout[-2000:]}"

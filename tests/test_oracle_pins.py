@@ -293,6 +293,32 @@ def test_sor_matches_dense_lu(orc, n):
         assert np.abs(orc.interior(u) - x).max() < 1e-12
 
 
+def test_stopping_rule_is_first_iterate_below_tol(orc):
+    """The stopping rule as read from Sec. 3.2.2 (a residual criterion; the
+    norm is not named): the relative L2 residual ||b - A u^(k)|| / ||b|| over
+    the interior rows, tested after every iteration, stops at the first k where
+    it is <= tol.  Checked against the dense system built independently: the
+    returned iterate meets the rule, its reported residual is that iterate's,
+    and the iterate one before does not meet it."""
+    n = (5, 4, 3, 3)
+    G, w = _step_inputs(orc, n, 17)
+    coef, b = orc.assemble(n, G, w, 1.0, 1e-2, 0.5)
+    A, bb = orc.dense_system(n, coef, b)
+
+    def rel(u):
+        return np.linalg.norm(bb - A @ orc.interior(u).ravel()) / np.linalg.norm(bb)
+
+    for order in (orc.LEX, orc.RB):
+        for tol in (1e-4, 1e-9):
+            u, k, rr, st = orc.sor(n, coef, b, w, 1.5, tol, 10000, order)
+            assert st == 0 and k >= 2, (order, tol, k, st)
+            assert rel(u) <= tol * (1.0 + 1e-9)
+            assert abs(rr - rel(u)) <= 1e-6 * rel(u)
+            u1, k1, _, st1 = orc.sor(n, coef, b, w, 1.5, 0.0, k - 1, order)
+            assert k1 == k - 1 and st1 == 1
+            assert rel(u1) > tol
+
+
 def test_lex_and_rb_same_fixed_point(orc):
     n = (8, 7, 6, 4)
     G, w = _step_inputs(orc, n, 9)
