@@ -217,7 +217,10 @@ def test_prepare_wide_rows():
 
 
 RAGGED = [(1, 1, 1, 1), (2, 1, 1, 1), (3, 2, 2, 2), (5, 4, 3, 3), (7, 6, 5, 4), (4, 3, 3, 2),
-          (130, 3, 2, 2), (129, 4, 2, 3), (64, 5, 3, 2), (33, 9, 7, 3)]
+          (130, 3, 2, 2), (129, 4, 2, 3), (64, 5, 3, 2), (33, 9, 7, 3),
+          # wide rows with more frames than the sweep holds back before writing
+          # (8), not a multiple of it, and more rows than one block (16)
+          (133, 37, 5, 13), (257, 19, 3, 9)]
 
 
 def random_system(n, seed, tau=0.5):
@@ -584,32 +587,40 @@ def test_sweep_forms_and_grids_give_the_same_bits(monkeypatch):
     colour, the fixed-count solve tests no stopping rule, and each cell's
     arithmetic is the same in every form.  Also the mixed step at several
     grids of its FP32 sweep: same iterate, passes and inner iterations."""
-    n = (131, 10, 6, 4)                   # two-cell rows (>= 64 slots), ragged in every axis
-    rng = np.random.default_rng(77)
-    G = T(rng.uniform(0.05, 1.0, size=(4,) + B.padded_shape(n)))
-    w = np.zeros(B.padded_shape(n))
-    w[1:-1, 1:-1, 1:-1, 1:-1] = rng.uniform(0.0, 1.0, size=B.interior_shape(n))
-    ws = B.alloc_workspace(n, 0, B.MIXED)
-    sp = B.StepParams(fixed_iters=9, rescale=False, omega=1.7)
     forms = [{}, {"SUBSURF4D_SWEEP": "r"}, {"SUBSURF4D_SWEEP": "t"}, {"SUBSURF4D_SWEEP": "8"},
              {"SUBSURF4D_SWEEP": "p"}, {"SUBSURF4D_SWEEP": "d"}, {"SUBSURF4D_SWEEP": "D"},
              {"SUBSURF4D_SWEEP_GRID": "13"}, {"SUBSURF4D_SWEEP_GRID": "100"}, {"SUBSURF4D_SWEEP_GRID": "300"},
              {"SUBSURF4D_ASM_PREFETCH": "0"}, {"SUBSURF4D_ASM_NT": "0"}]
     keys = {k for f in forms for k in f}
-    ref = None
-    for f in forms:
+    # two-cell rows (>= 64 slots), ragged in every axis; the second with 13
+    # frames (a held-back group of 8 and a tail of 5) and 37 rows (3 blocks)
+    for n in ((131, 10, 6, 4), (133, 37, 5, 13)):
+        rng = np.random.default_rng(77)
+        G = T(rng.uniform(0.05, 1.0, size=(4,) + B.padded_shape(n)))
+        w = np.zeros(B.padded_shape(n))
+        w[1:-1, 1:-1, 1:-1, 1:-1] = rng.uniform(0.0, 1.0, size=B.interior_shape(n))
+        ws = B.alloc_workspace(n, 0, B.MIXED)
+        sp = B.StepParams(fixed_iters=9, rescale=False, omega=1.7)
+        ref = None
+        for f in forms:
+            for k in keys:
+                monkeypatch.delenv(k, raising=False)
+            for k, v in f.items():
+                monkeypatch.setenv(k, v)
+            u, r = step_gpu(n, G, w, None, 0, None, sp, ws)
+            assert r["iterations"] == 9, (n, f, r)
+            if ref is None:
+                ref = u
+            else:
+                assert np.array_equal(u, ref), (n, f)
         for k in keys:
             monkeypatch.delenv(k, raising=False)
-        for k, v in f.items():
-            monkeypatch.setenv(k, v)
-        u, r = step_gpu(n, G, w, None, 0, None, sp, ws)
-        assert r["iterations"] == 9, (f, r)
-        if ref is None:
-            ref = u
-        else:
-            assert np.array_equal(u, ref), f
-    for k in keys:
-        monkeypatch.delenv(k, raising=False)
+    n = (131, 10, 6, 4)
+    rng = np.random.default_rng(77)
+    G = T(rng.uniform(0.05, 1.0, size=(4,) + B.padded_shape(n)))
+    w = np.zeros(B.padded_shape(n))
+    w[1:-1, 1:-1, 1:-1, 1:-1] = rng.uniform(0.0, 1.0, size=B.interior_shape(n))
+    ws = B.alloc_workspace(n, 0, B.MIXED)
     msp = B.StepParams(precision=B.MIXED, rescale=False, refine_tol=1e-11, inner_sweeps=6, omega=1.7)
     mref = None
     for g in (None, "20", "75", "250"):
