@@ -78,6 +78,14 @@ __global__ __launch_bounds__(kBlock) void kb_split_u(BTable T)
     });
 }
 
+// Store of a batched assembly output, non-temporal when NT.
+template <bool NT, typename P, typename V>
+__device__ __forceinline__ void kput(P* p, V v)
+{
+    if (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // Assembly of every job, frame-marching: a work item is 256 consecutive
 // (i,j,k) positions of one frame, and each thread walks the frames l = 1..N4
 // of its position.  The values of u at the position and its six x/y/z
@@ -88,6 +96,13 @@ __global__ __launch_bounds__(kBlock) void kb_split_u(BTable T)
 // records, r/D of the initial iterate, and one partial of ||b||^2 and of the
 // initial residual per wave and item (a job's partials do not depend on the
 // rest of the batch).
+// FAST: the -t face's q and 1/sqrt(eps^2 + q) are carried from the frame
+// below, where the same thread formed them, from the same values in the same
+// order, as its +t face (same bits), and the outputs are written with
+// non-temporal stores, so they do not push the u rows that the neighbouring
+// items are about to read out of L2.  MIXED: also the BF16 records and r/D
+// of the initial iterate, which only the mixed-precision form reads.
+template <bool FAST, bool MIXED>
 __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
 {
     for_runs(T.int_start, nullptr, T.n_jobs, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
@@ -127,7 +142,9 @@ __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
                 axis(p0, Am);
                 axis(p0 + sd[3], Ac);
                 double gt_below = G[3u * npad + p0];
+                double tq = 0.0, trs = 0.0;            // the +t face of the frame below (FAST)
                 for (int l = 1; l <= J.n4; ++l) {
+                    const bool carried = FAST && l > 1;
                     const uint32_t p = p0 + (uint32_t)l * sd[3];
                     axis(p + sd[3], Ap);
                     double dxy[2][2], dxz[2][2], dyz[2][2];   // in-frame diagonals [-/+][-/+]
@@ -165,6 +182,7 @@ __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
                     for (int d = 0; d < 4; ++d) { wm[d] = w1(d, -1); wp[d] = w1(d, 1); }
 #pragma unroll
                     for (int d = 0; d < 4; ++d) {
+                        const bool skip_m = d == 3 && carried;
                         const double gnm = (w0 - wm[d]) * J.inv_h;
                         const double gnp = (wp[d] - w0) * J.inv_h;
                         double qm = gnm * gnm, qp = gnp * gnp;
@@ -172,14 +190,16 @@ __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
                         for (int t = 0; t < 4; ++t) {
                             if (t == d) continue;
                             const double wpt = wp[t], wmt = wm[t];
-                            const double dm_pt = w2(d, -1, t, 1), dm_mt = w2(d, -1, t, -1);
                             const double dp_pt = w2(d, 1, t, 1), dp_mt = w2(d, 1, t, -1);
-                            const double tm = ((dm_pt + wpt) - (dm_mt + wmt)) * (0.25 * J.inv_h);
                             const double tp = ((wpt + dp_pt) - (wmt + dp_mt)) * (0.25 * J.inv_h);
-                            qm += tm * tm;
                             qp += tp * tp;
+                            if (!skip_m) {
+                                const double dm_pt = w2(d, -1, t, 1), dm_mt = w2(d, -1, t, -1);
+                                const double tm = ((dm_pt + wpt) - (dm_mt + wmt)) * (0.25 * J.inv_h);
+                                qm += tm * tm;
+                            }
                         }
-                        q[2 * d] = qm;
+                        q[2 * d] = skip_m ? tq : qm;
                         q[2 * d + 1] = qp;
                     }
                     double qs = 0.0;
@@ -192,8 +212,11 @@ __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
                     for (int d = 0; d < 4; ++d) {
                         const double gm = d == 3 ? gt_below : G[(uint32_t)d * npad + p - sd[d]];
                         const double gp = d == 3 ? gt_here : G[(uint32_t)d * npad + p];
-                        c[2 * d] = scale * gm * rsqrt(J.eps2 + q[2 * d]);
-                        c[2 * d + 1] = scale * gp * rsqrt(J.eps2 + q[2 * d + 1]);
+                        const double rm = (d == 3 && carried) ? trs : rsqrt(J.eps2 + q[2 * d]);
+                        const double rp = rsqrt(J.eps2 + q[2 * d + 1]);
+                        c[2 * d] = scale * gm * rm;
+                        c[2 * d + 1] = scale * gp * rp;
+                        if (d == 3) { tq = q[7]; trs = rp; }
                     }
                     gt_below = gt_here;
                     double D = 1.0, bfull = w0, off = 0.0;
@@ -212,17 +235,19 @@ __global__ __launch_bounds__(kBlock) void kb_assemble(BTable T)
                     const uint32_t qf = irow * (uint32_t)J.half + m;
                     const uint32_t ci = bctile(J, colour, qf);
 #pragma unroll
-                    for (int f = 0; f < 8; ++f) coef[ci + f * kTileSlots] = c[f];
-                    coef[ci + 8 * kTileSlots] = w0;
-                    const double inv = 1.0 / D;
-                    // scaled residual of the initial iterate: the first refinement pass starts from it
-                    rf[(uint32_t)colour * (uint32_t)J.ntq * kTileSlots + qf] = (float)(r0 / D);
-                    uint32_t hb[8];
+                    for (int f = 0; f < 8; ++f) kput<FAST>(&coef[ci + f * kTileSlots], c[f]);
+                    kput<FAST>(&coef[ci + 8 * kTileSlots], w0);
+                    if (MIXED) {
+                        const double inv = 1.0 / D;
+                        // scaled residual of the initial iterate: the first refinement pass starts from it
+                        kput<FAST>(&rf[(uint32_t)colour * (uint32_t)J.ntq * kTileSlots + qf], (float)(r0 / D));
+                        uint32_t hb[8];
 #pragma unroll
-                    for (int f = 0; f < 8; ++f) hb[f] = bf16_bits((float)(c[f] * inv));
-                    const u32x4 rec = {hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16), hb[4] | (hb[5] << 16),
-                                       hb[6] | (hb[7] << 16)};
-                    c16[(uint32_t)colour * (uint32_t)J.ntq * kTileSlots + qf] = rec;
+                        for (int f = 0; f < 8; ++f) hb[f] = bf16_bits((float)(c[f] * inv));
+                        const u32x4 rec = {hb[0] | (hb[1] << 16), hb[2] | (hb[3] << 16), hb[4] | (hb[5] << 16),
+                                           hb[6] | (hb[7] << 16)};
+                        kput<FAST>(&c16[(uint32_t)colour * (uint32_t)J.ntq * kTileSlots + qf], rec);
+                    }
 #pragma unroll
                     for (int e = 0; e < 7; ++e) { Am[e] = Ac[e]; Ac[e] = Ap[e]; }
                 }
@@ -891,7 +916,15 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
     SS4_HIP(hipMemcpyAsync(T.both_start, both_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
     SS4_HIP(hipMemcpyAsync(T.ball_start, ball_start.data(), sizeof(int64_t) * (n_jobs + 1), hipMemcpyHostToDevice, s));
 
-    const int g_asm = resident_grid(reinterpret_cast<const void*>(&kb_assemble));
+    // SUBSURF4D_KB_ASM=0 selects the assembly without the carried -t face and
+    // with plain stores (same bits)
+    const char* env_asm = getenv("SUBSURF4D_KB_ASM");
+    const bool asm_fast = !(env_asm && env_asm[0] == '0');
+    const void* kasm = asm_fast ? (fp64 ? reinterpret_cast<const void*>(&kb_assemble<true, false>)
+                                        : reinterpret_cast<const void*>(&kb_assemble<true, true>))
+                                : (fp64 ? reinterpret_cast<const void*>(&kb_assemble<false, false>)
+                                        : reinterpret_cast<const void*>(&kb_assemble<false, true>));
+    const int g_asm = resident_grid(kasm);
     const int g_res = resident_grid(reinterpret_cast<const void*>(&kb_residual));
     const int g_up = resident_grid(reinterpret_cast<const void*>(&kb_update));
     const dim3 g_zero(64, n_jobs < 65535 ? n_jobs : 65535);
@@ -899,7 +932,10 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
     kb_init<<<(n_jobs + 255) / 256, 256, 0, s>>>(T, fp64 ? sp.tol : sp.refine_tol, T.max_outer);
     const int g_dec = n_jobs < 4096 ? n_jobs : 4096;
     kb_split_u<<<g_up, kBlock, 0, s>>>(T);
-    kb_assemble<<<g_asm, kBlock, 0, s>>>(T);
+    if (asm_fast && fp64) kb_assemble<true, false><<<g_asm, kBlock, 0, s>>>(T);
+    else if (asm_fast) kb_assemble<true, true><<<g_asm, kBlock, 0, s>>>(T);
+    else if (fp64) kb_assemble<false, false><<<g_asm, kBlock, 0, s>>>(T);
+    else kb_assemble<false, true><<<g_asm, kBlock, 0, s>>>(T);
     kb_assemble_decide<<<g_dec, kBlock, 0, s>>>(T);
     kb_compact<<<1, kScan, 0, s>>>(T);
     if (!fp64) kb_zero_d<<<g_zero, 256, 0, s>>>(T);
