@@ -486,7 +486,9 @@ def main():
     del lab, d2, tcells
     torch.cuda.empty_cache()
     ct = counter_traffic()
-    if ct is not None:
+    # the summary's counters hold for its own workload only (the full volume):
+    # another grid (a --frames run) reports no traffic
+    if ct is not None and ct.get("algorithmic_bytes_per_launch") == out["roofline"]["bytes_per_launch"]:
         out["roofline"]["traffic"] = ct["hbm_bytes_per_launch"]
         out["roofline"]["traffic_source"] = COUNTER_SUMMARY
     mixed_steps = args.steps if args.mixed_steps < 0 else args.mixed_steps

@@ -292,7 +292,8 @@ __global__ __launch_bounds__(kBlock) void kb_assemble_decide(BTable T)
 // colour's t-neighbours and one x-neighbour stay in registers.  Writes r/D
 // (FP32, the rhs of the correction sweeps) and one partial sum of r^2 per
 // wave and item; the partials of a job do not depend on the rest of the
-// batch.
+// batch.  MIXED: r/D is written (the FP64 form only needs the sums).
+template <bool MIXED>
 __global__ __launch_bounds__(kBlock) void kb_residual(BTable T)
 {
     for_runs(T.act_colf, T.act_jobs, *T.n_act, [&](int jb, uint32_t i0, uint32_t i1, uint32_t step) {
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void kb_residual(BTable T)
                             const double D = ((((((((1.0 + c0) + c1) + c2) + c3) + c4) + c5) + c6) + c7);
                             const double res = s - D * own[ui];
                             acc += res * res;
-                            rf[cb + q] = (float)(res / D);
+                            if (MIXED) rf[cb + q] = (float)(res / D);
                         }
                         Bm = Bc;
                         Bc = Bp;
@@ -925,7 +926,8 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
                                 : (fp64 ? reinterpret_cast<const void*>(&kb_assemble<false, false>)
                                         : reinterpret_cast<const void*>(&kb_assemble<false, true>));
     const int g_asm = resident_grid(kasm);
-    const int g_res = resident_grid(reinterpret_cast<const void*>(&kb_residual));
+    const int g_res = resident_grid(fp64 ? reinterpret_cast<const void*>(&kb_residual<false>)
+                                         : reinterpret_cast<const void*>(&kb_residual<true>));
     const int g_up = resident_grid(reinterpret_cast<const void*>(&kb_update));
     const dim3 g_zero(64, n_jobs < 65535 ? n_jobs : 65535);
 
@@ -1052,7 +1054,8 @@ int run_batch_step_on(const subsurf4d_batch_job* jobs, int n_jobs, const subsurf
             kb_update<<<g_up, kBlock, 0, s>>>(T);
         }
         kb_next_pass<<<1, 64, 0, s>>>(T);
-        kb_residual<<<g_res, kBlock, 0, s>>>(T);
+        if (fp64) kb_residual<false><<<g_res, kBlock, 0, s>>>(T);
+        else kb_residual<true><<<g_res, kBlock, 0, s>>>(T);
         kb_residual_decide<<<g_dec, kBlock, 0, s>>>(T);
         kb_compact<<<1, kScan, 0, s>>>(T);
     };
