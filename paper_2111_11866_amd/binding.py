@@ -527,7 +527,8 @@ def track(n, u, level, capacity=1 << 16, join_radius=None, label=None, dist2=Non
                                  int(capacity), ctypes.byref(k), _p(ws, "workspace"), _nb(ws), _stream(stream)))
     if join_radius is not None:
         _check(lib().subsurf4d_track_join(ctypes.byref(grid(n)), cells, k.value, float(join_radius)))
-    out = np.frombuffer(bytes(cells)[: k.value * ctypes.sizeof(CellC)], dtype=CELL_DTYPE).copy()
+    out = np.frombuffer(ctypes.string_at(ctypes.addressof(cells), k.value * ctypes.sizeof(CellC)),
+                        dtype=CELL_DTYPE).copy()
     return out, label, dist2
 
 

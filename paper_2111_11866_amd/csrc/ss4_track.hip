@@ -433,6 +433,27 @@ int run_track_join(const int32_t n[4], subsurf4d_cell* cells, int32_t nc, double
     };
     const double r2 = radius * radius;
     std::vector<char> used(parts.size(), 0);
+    // candidates S by the frame of their last cell, with that cell's name, its
+    // point and its forward prolongation (the choice below is a strict order
+    // on (distance, name), so the order of the candidates does not matter)
+    struct End { size_t s; int32_t name; int64_t e0[3], fwd[3]; };
+    std::vector<std::vector<End>> ending((size_t)(n[3] > 0 ? n[3] : 1));
+    for (size_t sidx = 0; sidx < parts.size(); ++sidx) {
+        const int32_t last = parts[sidx].cells.back();
+        End e;
+        e.s = sidx;
+        e.name = cells[last].name;
+        xyz(last, e.e0);
+        if (parts[sidx].cells.size() > 1) {
+            int64_t e1[3];
+            xyz(parts[sidx].cells[parts[sidx].cells.size() - 2], e1);
+            for (int a = 0; a < 3; ++a) e.fwd[a] = 2 * e.e0[a] - e1[a];
+        } else {
+            for (int a = 0; a < 3; ++a) e.fwd[a] = e.e0[a];
+        }
+        const int32_t fl = cells[last].frame;
+        if (fl >= 0 && fl < n[3]) ending[(size_t)fl].push_back(e);
+    }
     std::vector<size_t> tord(parts.size());
     for (size_t t = 0; t < parts.size(); ++t) tord[t] = t;
     std::sort(tord.begin(), tord.end(),
@@ -440,7 +461,7 @@ int run_track_join(const int32_t n[4], subsurf4d_cell* cells, int32_t nc, double
     for (size_t t : tord) {
         const int32_t first = parts[t].cells[0];
         const int32_t f = cells[first].frame;
-        if (f == 0) continue;
+        if (f <= 0 || f > n[3]) continue;     // no frame before it (or a record outside the grid)
         int64_t c0[3], back[3];
         xyz(first, c0);
         if (parts[t].cells.size() > 1) {
@@ -453,30 +474,19 @@ int run_track_join(const int32_t n[4], subsurf4d_cell* cells, int32_t nc, double
         int64_t best_d = -1;
         int32_t best_last = -1;
         size_t best_s = 0;
-        for (size_t sidx = 0; sidx < parts.size(); ++sidx) {
-            if (used[sidx] || sidx == t) continue;
-            const int32_t last = parts[sidx].cells.back();
-            if (cells[last].frame != f - 1) continue;
-            int64_t e0[3], fwd[3];
-            xyz(last, e0);
-            if (parts[sidx].cells.size() > 1) {
-                int64_t e1[3];
-                xyz(parts[sidx].cells[parts[sidx].cells.size() - 2], e1);
-                for (int a = 0; a < 3; ++a) fwd[a] = 2 * e0[a] - e1[a];
-            } else {
-                for (int a = 0; a < 3; ++a) fwd[a] = e0[a];
-            }
+        for (const End& e : ending[(size_t)(f - 1)]) {
+            if (used[e.s] || e.s == t) continue;
             int64_t d1 = 0, d2 = 0;
             for (int a = 0; a < 3; ++a) {
-                d1 += (back[a] - e0[a]) * (back[a] - e0[a]);
-                d2 += (fwd[a] - c0[a]) * (fwd[a] - c0[a]);
+                d1 += (back[a] - e.e0[a]) * (back[a] - e.e0[a]);
+                d2 += (e.fwd[a] - c0[a]) * (e.fwd[a] - c0[a]);
             }
             const int64_t d = d1 < d2 ? d1 : d2;
             if ((double)d > r2) continue;
-            if (best_d < 0 || d < best_d || (d == best_d && cells[last].name < best_last)) {
+            if (best_d < 0 || d < best_d || (d == best_d && e.name < best_last)) {
                 best_d = d;
-                best_last = cells[last].name;
-                best_s = sidx;
+                best_last = e.name;
+                best_s = e.s;
             }
         }
         if (best_d >= 0) {

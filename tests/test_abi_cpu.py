@@ -205,3 +205,64 @@ int main(void)
     assert out.returncode == 0, (out.returncode, out.stderr)
     ws = int(out.stdout.split()[0])
     assert ws == B.workspace_bytes((40, 30, 20, 5), 3, B.FP64)
+
+
+def _random_cells(rng, n, per_frame, p_link):
+    """A random cell list as the tracking produces it: names are distinct
+    voxel indices of their frame (in increasing order), centres voxels of the
+    same frame, and links name a cell of the frame before (kind 1) or none;
+    no cell is linked to twice, so every trajectory is a simple chain."""
+    n1, n2, n3, n4 = n
+    fsz = n1 * n2 * n3
+    recs = []
+    prev_names = []
+    for f in range(n4):
+        k = int(rng.integers(1, per_frame + 1))
+        names = np.sort(rng.choice(fsz, size=k, replace=False)) + f * fsz
+        cur = []
+        for nm in names:
+            centre = f * fsz + int(rng.integers(0, fsz))
+            link = -1
+            if prev_names and rng.random() < p_link:
+                link = int(prev_names.pop(int(rng.integers(0, len(prev_names)))))
+            recs.append((int(nm), f, centre, int(rng.integers(0, 50)), link, 1 if link >= 0 else 0))
+            cur.append(int(nm))
+        prev_names = cur
+    return np.array(recs, dtype=[("name", "<i4"), ("frame", "<i4"), ("centre", "<i4"), ("dist2", "<i4"),
+                                 ("prev", "<i4"), ("kind", "<i4")])
+
+
+@pytest.mark.parametrize("seed,radius", [(1, 3.0), (2, 6.0), (3, 12.0), (4, 0.0)])
+def test_track_join_matches_oracle(seed, radius):
+    """subsurf4d_track_join is host code: on random cell lists (links with
+    branching, single cells, gaps) its joined trajectories equal the oracle's
+    reading of the joining step of Sec. 5."""
+    import ctypes
+
+    import oracle as orc
+    from paper_2111_11866_amd import binding as B
+
+    rng = np.random.default_rng(seed)
+    n = (23, 17, 11, 7)
+    ref_cells = _random_cells(rng, n, 40, 0.6)
+    ref = orc.track_join(n, ref_cells, radius)
+    arr = (B.CellC * len(ref_cells))()
+    for q, c in enumerate(ref_cells):
+        arr[q] = B.CellC(*(int(v) for v in c))
+    rc = B.lib().subsurf4d_track_join(ctypes.byref(B.grid(n)), arr, len(ref_cells), float(radius))
+    assert rc == 0
+    got = np.frombuffer(ctypes.string_at(ctypes.addressof(arr), len(ref_cells) * ctypes.sizeof(B.CellC)),
+                        dtype=B.CELL_DTYPE)
+    by = {int(c["name"]): c for c in got}
+    linked = {int(c["prev"]) for c in got if c["prev"] >= 0}
+    chains = []
+    for c in got:
+        if int(c["name"]) in linked:
+            continue
+        ch = [int(c["name"])]
+        while by[ch[-1]]["prev"] >= 0:
+            ch.append(int(by[ch[-1]]["prev"]))
+        chains.append(ch[::-1])
+    assert sorted(chains, key=lambda ch: ch[0]) == ref
+    if radius >= 12.0:
+        assert int((got["kind"] == 3).sum()) > 0     # the case exercises the joining
