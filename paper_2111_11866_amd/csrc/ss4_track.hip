@@ -272,12 +272,22 @@ __global__ __launch_bounds__(kBlock) void kt_overlap_best(const int32_t* __restr
 
 }  // namespace
 
+// Entries of the (missed cell x cell) overlap table: at least
+// kTrackTableEntries and the capacity, and half the voxel count, so that on a
+// volume one or two row chunks (each a pass over the labels) cover every
+// missed cell.
+static int64_t track_table_entries(int64_t nint, int32_t capacity)
+{
+    const int64_t t = capacity > kTrackTableEntries ? capacity : kTrackTableEntries;
+    return t > nint / 2 ? t : nint / 2;
+}
+
 size_t track_workspace_bytes(const int32_t n[4], int32_t capacity)
 {
     const int64_t N = (int64_t)n[0] * n[1] * n[2] * n[3];
     const int64_t blocks = (N + kRange - 1) / kRange;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t table = (size_t)(capacity > kTrackTableEntries ? capacity : kTrackTableEntries);
+    const size_t table = (size_t)track_table_entries(N, capacity);
     return al(4 * (size_t)N) * 2 + al(4 * (size_t)(blocks + 1)) * 2 + al(8 * (size_t)capacity) +
            al(4 * (size_t)capacity) * 6 + al(table * 4);
 }
@@ -348,7 +358,8 @@ int run_track(const int32_t n[4], const double* u, double level, int32_t* lab, i
     if (M > 0) {
         SS4_HIP(hipMemcpyAsync(row_of, hrow.data(), 4 * (size_t)K, hipMemcpyHostToDevice, s));
         SS4_HIP(hipMemcpyAsync(row_cell, hrcell.data(), 4 * (size_t)M, hipMemcpyHostToDevice, s));
-        const int32_t rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(M, kTrackTableEntries / K));
+        const int32_t rows =
+            (int32_t)std::max<int64_t>(1, std::min<int64_t>(M, track_table_entries(g.nint, capacity) / K));
         for (int32_t r0 = 0; r0 < M; r0 += rows) {
             const int32_t nr = std::min(rows, M - r0);
             kt_zero_i32<<<grid_for((int64_t)nr * K), kBlock, 0, s>>>(table, (int64_t)nr * K);
