@@ -358,8 +358,15 @@ int run_track(const int32_t n[4], const double* u, double level, int32_t* lab, i
     if (M > 0) {
         SS4_HIP(hipMemcpyAsync(row_of, hrow.data(), 4 * (size_t)K, hipMemcpyHostToDevice, s));
         SS4_HIP(hipMemcpyAsync(row_cell, hrcell.data(), 4 * (size_t)M, hipMemcpyHostToDevice, s));
-        const int32_t rows =
-            (int32_t)std::max<int64_t>(1, std::min<int64_t>(M, track_table_entries(g.nint, capacity) / K));
+        // SUBSURF4D_TRACK_TABLE=<entries> caps the table (more, smaller row
+        // chunks; the same records)
+        int64_t tab = track_table_entries(g.nint, capacity);
+        const char* ev = getenv("SUBSURF4D_TRACK_TABLE");
+        if (ev) {
+            const long long v = atoll(ev);
+            if (v > 0 && v < tab) tab = v;
+        }
+        const int32_t rows = (int32_t)std::max<int64_t>(1, std::min<int64_t>(M, tab / K));
         for (int32_t r0 = 0; r0 < M; r0 += rows) {
             const int32_t nr = std::min(rows, M - r0);
             kt_zero_i32<<<grid_for((int64_t)nr * K), kBlock, 0, s>>>(table, (int64_t)nr * K);

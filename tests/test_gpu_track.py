@@ -118,3 +118,20 @@ def test_track_nuclei_crop_against_oracle_and_edt():
     ref_cells = orc.track_cells(n, ref_lab, ref_d2)
     same_cells(cells, ref_cells)
     assert len(cells) > 100 and (cells["kind"][cells["frame"] > 0] > 0).mean() > 0.5
+
+
+@pytest.mark.parametrize("entries", ["1", "2580", "12900"])   # 1, 2 and 10 rows per chunk
+def test_track_overlap_row_chunks_same_records(monkeypatch, entries):
+    """The overlap links computed in many row chunks of the (missed cell x
+    cell) table (its size capped by SUBSURF4D_TRACK_TABLE) equal the
+    one-chunk records and the oracle's."""
+    n, level = (40, 23, 12, 3), 0.62
+    u = np.random.default_rng(4).uniform(0.0, 1.0, size=orc.padded_shape(n))
+    monkeypatch.delenv("SUBSURF4D_TRACK_TABLE", raising=False)
+    one, _, _ = gpu_track(n, u, level)
+    assert (one["kind"] == 2).sum() > 10          # the case has overlap links
+    monkeypatch.setenv("SUBSURF4D_TRACK_TABLE", entries)
+    many, lab, d2 = gpu_track(n, u, level)
+    monkeypatch.delenv("SUBSURF4D_TRACK_TABLE", raising=False)
+    assert np.array_equal(many, one)
+    same_cells(many, orc.track_cells(n, lab, d2))
