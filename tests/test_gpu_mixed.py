@@ -68,7 +68,11 @@ def test_mixed_steps_cfg1(cfg1):
         print(row)
 
 
-@pytest.mark.parametrize("n", [(5, 4, 3, 3), (7, 6, 5, 4), (33, 9, 7, 3), (130, 5, 3, 3), (129, 6, 4, 3), (257, 4, 3, 2)])
+@pytest.mark.parametrize("n", [(5, 4, 3, 3), (7, 6, 5, 4), (33, 9, 7, 3), (130, 5, 3, 3), (129, 6, 4, 3), (257, 4, 3, 2),
+                               # degenerate extents (a row with one cell, or none, of a colour) and
+                               # a wide grid with 13 frames and rows beyond one tile of rows
+                               (1, 1, 1, 1), (2, 1, 1, 1), (1, 3, 1, 2), (3, 2, 2, 1), (130, 1, 1, 1),
+                               (133, 20, 3, 13)])
 def test_mixed_solve_ragged(n):
     rng = np.random.default_rng(sum(n))
     G = rng.uniform(0.05, 1, size=(4,) + B.padded_shape(n))
