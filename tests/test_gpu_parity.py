@@ -371,6 +371,40 @@ def test_step_teacher_forced_cfg1(cfg1):
     print("worst per-step max-abs vs oracle:", worst)
 
 
+def test_step_teacher_forced_wide_window():
+    """A nuclei window with wide rows (the two-cell sweep in 16-row blocks),
+    27 rows, 11 frames (a held-back write group of 8 frames and a tail of 3),
+    balls and rescale: the oracle's preparation, then 4 steps each from the
+    oracle's u^{resc;n-1}, the GPU within 1e-10 of the red-black oracle."""
+    img = synth.window_job((131, 27, 13, 11), 7, 70007)
+    pp = B.PrepareParams(ball_r=8.0, image_scale=1.0 / 255.0)
+    n = img.n
+    prep = orc.prepare(n, img.image.astype(np.float64) / 255.0, img.centres, orc_pp(pp))
+    sp = B.StepParams(omega=1.6)
+    osp = orc.StepParams(omega=1.6)
+    G_np = prep["G"]
+    G = T(G_np)
+    owner = T(prep["owner"])
+    cen, nc = B.centres_tensor(img.centres)
+    ws = B.alloc_workspace(n, nc)
+    w = orc.rescale(n, orc.init_u(n, img.seeds, 1.0, 0.0), img.centres, sp.ball_r, prep["owner"])
+    for s in range(4):
+        rec = orc.step(n, G_np, w, img.centres, prep["owner"], osp, orc.RB)
+        ug, r = step_gpu(n, G, w, cen, nc, owner, sp, ws)
+        assert r["status"] == 0
+        if r["iterations"] != rec["iterations"]:
+            k = rec["iterations"]
+            kmin = min(k, r["iterations"])
+            near = orc.step(n, G_np, w, img.centres, prep["owner"], osp, orc.RB, fixed_iters=kmin)
+            assert abs(near["rel_res"] / osp.tol - 1) < 1e-6, (s, r, k, near["rel_res"])
+            rec = orc.step(n, G_np, w, img.centres, prep["owner"], osp, orc.RB, fixed_iters=k)
+            ug, r = step_gpu(n, G, w, cen, nc, owner, replace(sp, fixed_iters=k), ws)
+        assert r["iterations"] >= 2
+        err = np.abs(ug - rec["u_resc"]).max()
+        assert err <= 1e-10, (s, err)
+        w = rec["u_resc"]
+
+
 def test_step_vs_converged_lexicographic(cfg1):
     img, sp = cfg1["img"], cfg1["sp"]
     n = img.n
