@@ -106,3 +106,36 @@ def test_graph_captured_step_cfg1(cfg1):
         other.copy_(w0)
         B.step(n, 1.0, cfg1["G"], cfg1["cen"], cfg1["nc"], cfg1["owner"], other, B.StepParams(), ows)
         torch.cuda.synchronize()
+
+
+def test_graph_captured_step_wide_rows():
+    """Rows of >= 64 slots take the two-cell sweep in 16-row blocks with its
+    writes held in LDS; a captured FP64 step on such a grid (9 frames, 20 rows,
+    fixed count) matches the red-black oracle at 1e-10 on every replay."""
+    n = (130, 20, 6, 9)
+    rng = np.random.default_rng(11)
+    G_np = rng.uniform(0.05, 1.0, size=(4,) + B.padded_shape(n))
+    w_np = np.zeros(B.padded_shape(n))
+    w_np[1:-1, 1:-1, 1:-1, 1:-1] = rng.uniform(0.0, 1.0, size=B.interior_shape(n))
+    sp = B.StepParams(fixed_iters=25, rescale=False, omega=1.7)
+    ref = orc.step(n, G_np, w_np, None, None, orc.StepParams(omega=1.7, rescale=False), orc.RB, fixed_iters=25)
+    G, u, w0 = T(G_np), T(w_np), T(w_np)
+    ws = B.alloc_workspace(n)
+    res = B.result_tensor()
+    B.step_async(n, 1.0, G, None, 0, None, u, sp, ws, res)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        B.step_async(n, 1.0, G, None, 0, None, u, sp, ws, res)
+    for rep in range(3):
+        u.copy_(w0)
+        res.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        r = B.result_dict(res)
+        assert r["iterations"] == 25, (rep, r)
+        err = float(np.abs(u.cpu().numpy() - ref["u"]).max())
+        assert err <= 1e-10, (rep, err)
+        other = T(w_np)
+        B.step(n, 1.0, G, None, 0, None, other, sp, B.alloc_workspace(n))
+        torch.cuda.synchronize()
